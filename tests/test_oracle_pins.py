@@ -1,0 +1,335 @@
+"""Pins for the FP64 oracle: facts fixed by the paper and by mathematics,
+independent of the oracle's own formulas.
+
+Each test names the passage of arXiv:2309.04623 it checks and the kind of
+pin (worked value, closed form, invariant, library routine, brute force).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import nmf64, nnls, prng
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+def _tiny(seed, n=5, p=9, k=3, mask_frac=0.2):
+    g = np.random.default_rng(seed)
+    V = g.gamma(2.0, 1.0, (n, p))
+    M = g.uniform(0.2, 3.0, (n, p)) * (g.random((n, p)) >= mask_frac)
+    W = g.uniform(0.05, 1.0, (n, k))
+    H = g.uniform(0.05, 1.0, (k, p))
+    return V, M, W, H
+
+
+# ---------------------------------------------------------------- init (a2)
+
+def test_splitmix64_published_vectors():
+    """Counter-mode generator reproduces SplitMix64's published outputs."""
+    gold = _golden("splitmix64.json")
+    for vec in gold["vectors"]:
+        if "outputs_hex" in vec:
+            want = [int(x, 16) for x in vec["outputs_hex"]]
+        else:
+            want = vec["outputs"]
+        assert prng.splitmix64_outputs(vec["seed"], len(want)) == want
+
+
+def test_uniform_open_interval_exact_float32():
+    u = prng.uniform(7, prng.MAT_H, 200000)
+    assert u.min() > 0.0 and u.max() < 1.0
+    assert np.array_equal(u.astype(np.float32).astype(np.float64), u)
+    assert abs(u.mean() - 0.5) < 3e-3
+    # element i of a longer draw equals element i of a shorter one (counter mode)
+    assert np.array_equal(prng.uniform(7, prng.MAT_H, 10), u[:10])
+    assert not np.array_equal(prng.uniform(7, prng.MAT_W, 10), u[:10])
+
+
+# ---------------------------------------------------------- objective (a3)
+
+def test_objective_hand_worked_value():
+    """Eq. 2 weights the squared residual by V (here M) linearly."""
+    g = _golden("objective_2x2.json")
+    J = nmf64.objective(np.array(g["V"]), np.array(g["M"]), np.array(g["W"]), np.array(g["H"]))
+    assert J == g["J"]
+
+
+# -------------------------------------------------------- updates (a4, a5)
+
+@pytest.mark.parametrize("seed", range(100))
+def test_monotone_each_half_step(seed):
+    """Eq. 3's rules never increase the Eq. 2 cost (auxiliary-function
+    argument for weighted multiplicative updates), H-step and W-step alike."""
+    V, M, W, H = _tiny(seed)
+    Vh, Mw, _ = nmf64.prep(V, M)
+    J = nmf64.objective(Vh, Mw, W, H)
+    for _ in range(20):
+        H = nmf64.update_H(Vh, Mw, W, H)
+        J1 = nmf64.objective(Vh, Mw, W, H)
+        assert J1 <= J * (1 + 1e-13) + 1e-300
+        W = nmf64.update_W(Vh, Mw, W, H)
+        J2 = nmf64.objective(Vh, Mw, W, H)
+        assert J2 <= J1 * (1 + 1e-13) + 1e-300
+        J = J2
+        assert W.min() >= nmf64.EPS_FLOOR and H.min() >= nmf64.EPS_FLOOR
+
+
+@pytest.mark.parametrize("seed", [0, 1, 3])
+def test_planted_exact_low_rank_recovered(seed):
+    """V = W0 H0 exactly with K = K0: the iteration drives the relative cost
+    below 1e-10 (seed 2 of this family stalls in a local minimum; the method
+    is non-convex, Sec. 2)."""
+    g = np.random.default_rng(seed)
+    N, P, K = 6, 12, 2
+    W0 = g.uniform(0.5, 2.0, (N, K))
+    H0 = g.uniform(0.5, 2.0, (K, P))
+    H0[0, : P // 2] *= 0.1
+    H0[1, P // 2:] *= 0.1
+    V = W0 @ H0
+    M = np.ones_like(V)
+    M[g.random(V.shape) < 0.1] = 0
+    W = g.uniform(0.1, 1, (N, K))
+    H = g.uniform(0.1, 1, (K, P))
+    W, H, J = nmf64.build_basis(V, M, W, H, 3000)
+    Vh, Mw, _ = nmf64.prep(V, M)
+    assert J[-1] / np.sum(Mw * Vh ** 2) < 1e-10
+
+
+def test_planted_fixed_point():
+    """If W H reproduces the data, numerator equals denominator and one
+    iteration leaves (W, H) unchanged up to rounding."""
+    g = np.random.default_rng(11)
+    W0 = g.uniform(0.5, 2, (7, 3))
+    H0 = g.uniform(0.5, 2, (3, 10))
+    V = W0 @ H0
+    M = g.uniform(0.5, 2, V.shape)
+    W, H, _ = nmf64.build_basis(V, M, W0, H0, 1)
+    assert np.max(np.abs(W / W0 - 1)) < 1e-14
+    assert np.max(np.abs(H / H0 - 1)) < 1e-14
+
+
+def test_rank1_unweighted_reaches_svd():
+    """M = 1, K = 1: the optimum is the leading singular triple, which is
+    non-negative for a positive matrix (Perron); J* = ||V||^2 - s1^2."""
+    g = np.random.default_rng(5)
+    V = g.uniform(0.5, 2.0, (8, 11))
+    M = np.ones_like(V)
+    W, H, J = nmf64.build_basis(V, M, np.full((8, 1), 0.5), np.full((1, 11), 0.5), 500)
+    s = np.linalg.svd(V, compute_uv=False)
+    Jstar = np.sum(V ** 2) - s[0] ** 2
+    assert abs(J[-1] - Jstar) <= 1e-10 * np.sum(V ** 2)
+    U, S, Vt = np.linalg.svd(V)
+    best = S[0] * np.outer(np.abs(U[:, 0]), np.abs(Vt[0]))
+    assert np.max(np.abs(W @ H - best)) < 1e-6
+
+
+def test_eckart_young_lower_bound():
+    """M = 1: no rank-K product beats the truncated SVD, so every iterate's
+    cost is at least the sum of the discarded squared singular values."""
+    g = np.random.default_rng(6)
+    V = g.gamma(2.0, 1.0, (9, 14))
+    K = 3
+    s = np.linalg.svd(V, compute_uv=False)
+    bound = np.sum(s[K:] ** 2)
+    _, _, J = nmf64.build_basis(V, np.ones_like(V), g.uniform(0.1, 1, (9, K)),
+                                g.uniform(0.1, 1, (K, 14)), 300)
+    assert np.all(J >= bound * (1 - 1e-12))
+    assert J[-1] < J[0]
+
+
+def test_unweighted_lee_seung_association():
+    """With M = 1, W^T (W H) = (W^T W) H, so the H-rule equals the classic
+    unweighted form H o (W^T V) / (W^T W H) computed another way."""
+    V, _, W, H = _tiny(21)
+    M = np.ones_like(V)
+    h1 = nmf64.update_H(V, M, W, H)
+    h2 = H * (W.T @ V) / ((W.T @ W) @ H)
+    assert np.max(np.abs(h1 / h2 - 1)) < 1e-13
+    w1 = nmf64.update_W(V, M, W, h1)
+    w2 = W * (V @ h1.T) / (W @ (h1 @ h1.T))
+    assert np.max(np.abs(w1 / w2 - 1)) < 1e-13
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_H_rule_alone_reaches_columnwise_nnls(seed):
+    """With W fixed, the H-rule on column p is the projection iteration of
+    that column; its limit is the weighted NNLS minimiser, found here by
+    brute force over supports (K <= 4)."""
+    V, M, W, H = _tiny(100 + seed, n=7, p=5, k=3, mask_frac=0.15)
+    Vh, Mw, _ = nmf64.prep(V, M)
+    for _ in range(40000):
+        H = nmf64.update_H(Vh, Mw, W, H, eps=0.0)
+    for p in range(V.shape[1]):
+        G, b, c = nnls.normal_equations(W.T, Vh[:, p], Mw[:, p])
+        w_star, j_star = nnls.nnls_bruteforce(G, b, c)
+        j = nnls.cost(G, b, c, H[:, p])
+        assert j - j_star <= 1e-9 * max(j_star, 1e-12)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_W_rule_alone_reaches_rowwise_nnls(seed):
+    V, M, W, H = _tiny(200 + seed, n=5, p=8, k=3, mask_frac=0.15)
+    Vh, Mw, _ = nmf64.prep(V, M)
+    for _ in range(40000):
+        W = nmf64.update_W(Vh, Mw, W, H, eps=0.0)
+    for n in range(V.shape[0]):
+        G, b, c = nnls.normal_equations(H, Vh[n], Mw[n])
+        _, j_star = nnls.nnls_bruteforce(G, b, c)
+        assert nnls.cost(G, b, c, W[n]) - j_star <= 1e-9 * max(j_star, 1e-12)
+
+
+# ---------------------------------------------------------- invariances (a1)
+
+def test_weight_scaling_is_bitwise_invariant():
+    V, M, W, H = _tiny(31)
+    a = nmf64.build_basis(V, M, W, H, 30)
+    b = nmf64.build_basis(V, M * 8.0, W, H, 30)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_data_scaling_moves_into_H_bitwise():
+    V, M, W, H = _tiny(32)
+    a = nmf64.build_basis(V, M, W, H, 30)
+    b = nmf64.build_basis(V * 16.0, M, W, H * 16.0, 30)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1] * 16.0, b[1])
+
+
+def test_masked_garbage_is_ignored():
+    """Masked pixels are missing data (Sec. 4.1): NaN, Inf or negative values
+    under zero weight leave every iterate bitwise unchanged."""
+    V, M, W, H = _tiny(33)
+    Vg = V.copy()
+    holes = M == 0
+    vals = np.array([np.nan, np.inf, -5.0, 1e30])
+    Vg[holes] = vals[np.arange(holes.sum()) % 4]
+    a = nmf64.build_basis(V, M, W, H, 25)
+    b = nmf64.build_basis(Vg, M, W, H, 25)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_prep_flags_bad_data_under_weight():
+    V, M, _, _ = _tiny(34)
+    M[0, 0] = 1.0
+    bad = V.copy()
+    bad[0, 0] = np.nan
+    assert nmf64.prep(bad, M)[2] == "nonfinite"
+    bad[0, 0] = -1.0
+    assert nmf64.prep(bad, M)[2] == "negative"
+    M2 = M.copy()
+    M2[1, 1] = -0.5
+    assert nmf64.prep(V, M2)[2] == "negative_weight"
+    assert nmf64.prep(V, M)[2] == 0
+
+
+def test_fully_masked_row_and_column_keep_factors():
+    """A pixel masked in every image (den = 0) keeps its H column; an image
+    masked everywhere keeps its W row."""
+    V, M, W, H = _tiny(35)
+    M[:, 2] = 0
+    M[3, :] = 0
+    W1, H1, J = nmf64.build_basis(V, M, W, H, 10)
+    assert np.array_equal(H1[:, 2], H[:, 2])
+    assert np.array_equal(W1[3], W[3])
+    assert np.all(np.diff(J) <= 1e-12 * J[0])
+
+
+# ------------------------------------------------------- projection (a8)
+
+def test_projection_k1_one_step_closed_form():
+    """K = 1: one update from any c > 0 lands on sum m t h / sum m h^2."""
+    g = np.random.default_rng(41)
+    H = g.uniform(0.2, 2, (1, 30))
+    t = g.uniform(0, 3, (1, 30))
+    m = g.uniform(0, 2, (1, 30)) * (g.random((1, 30)) > 0.2)
+    c = nmf64.project(t, m, H, np.array([[0.37]]), 1)
+    want = np.sum(m * t * H) / np.sum(m * H * H)
+    assert abs(c[0, 0] / want - 1) < 1e-14
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_projection_limit_is_bruteforce_nnls(seed):
+    g = np.random.default_rng(300 + seed)
+    K, P = int(g.integers(1, 5)), 40
+    H = g.uniform(0.0, 1.0, (K, P)) ** 2
+    t = g.uniform(0.0, 1.0, (1, P)) + (g.uniform(0, 1, K) @ H)
+    m = g.uniform(0.1, 2.0, (1, P)) * (g.random((1, P)) > 0.1)
+    c = nmf64.project(t, m, H, np.full((1, K), 0.5), 60000, eps=0.0)
+    G, b, cc = nnls.normal_equations(H, t[0], m[0])
+    w_star, j_star = nnls.nnls_bruteforce(G, b, cc)
+    j = nnls.cost(G, b, cc, c[0])
+    assert j - j_star <= 1e-9 * j_star
+    if np.all(w_star > 1e-3 * w_star.max()):
+        assert np.linalg.norm(c[0] - w_star) <= 1e-6 * np.linalg.norm(w_star)
+
+
+def test_projection_limit_matches_scipy_nnls_k8():
+    g = np.random.default_rng(51)
+    K, P = 8, 120
+    H = g.gamma(1.0, 1.0, (K, P))
+    t = g.uniform(0, 0.2, (1, P)) + g.gamma(2, 1, K) @ H
+    m = 1.0 / (t + 0.01)
+    c = nmf64.project(t, m, H, np.full((1, K), 0.5), 20000)
+    w = nnls.nnls_scipy(H, t[0], m[0])
+    G, b, cc = nnls.normal_equations(H, t[0], m[0])
+    assert nnls.kkt_residual(G, b, w) < 1e-8
+    assert abs(nnls.cost(G, b, cc, c[0]) - nnls.cost(G, b, cc, w)) <= 1e-8 * nnls.cost(G, b, cc, w)
+    assert np.allclose(nnls.nnls_gram(G, b), w, rtol=1e-7, atol=1e-9)
+
+
+def test_gram_form_matches_direct_form():
+    g = np.random.default_rng(61)
+    K, P, F = 6, 200, 4
+    H = g.gamma(1.0, 1.0, (K, P))
+    T = g.gamma(2, 1, (F, K)) @ H + g.uniform(0, 0.1, (F, P))
+    MT = (1.0 / (T + 0.01)) * (g.random((F, P)) > 0.05)
+    C0 = prng.init_matrix(3, prng.MAT_C, F, K)
+    a = nmf64.project(T, MT, H, C0, 300)
+    b = nmf64.project_gram(T, MT, H, C0, 300)
+    assert np.max(np.abs(a / b - 1)) < 1e-12
+
+
+def test_ragged_projection_equals_dense_with_zero_weights():
+    g = np.random.default_rng(62)
+    K, P = 5, 64
+    H = g.gamma(1.0, 1.0, (K, P))
+    sizes = [10, 64, 33]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    pix = np.concatenate([np.sort(g.choice(P, s, replace=False)) for s in sizes]).astype(np.int32)
+    val = g.uniform(0, 3, offs[-1])
+    wt = g.uniform(0.5, 2, offs[-1])
+    C0 = prng.init_matrix(4, prng.MAT_C, 3, K)
+    T, MT = nmf64.ragged_to_dense(offs, pix, val, wt, P)
+    a = nmf64.project(T, MT, H, C0, 50)
+    b = nmf64.project_ragged(offs, pix, val, wt, H, C0, 50)
+    assert np.max(np.abs(a / b - 1)) < 1e-12
+
+
+# ------------------------------------------------------ subtraction (a9)
+
+def test_subtract_definition():
+    g = np.random.default_rng(71)
+    H = g.uniform(0, 1, (3, 20))
+    C = g.uniform(0, 1, (2, 3))
+    T = g.uniform(0, 2, (2, 20))
+    MT = (g.random((2, 20)) > 0.3).astype(float)
+    model, resid = nmf64.subtract(T, MT, H, C, scale=np.array([1.0, 0.5]))
+    assert np.allclose(model, np.einsum("fk,kp->fp", C, H), rtol=1e-15)
+    ok = MT > 0
+    assert np.all(np.isnan(resid[~ok]))
+    s = np.array([1.0, 0.5])[:, None] * np.ones_like(T)
+    assert np.allclose((resid + s * model)[ok], T[ok], rtol=1e-14)
+
+
+def test_normalisation_keeps_product():
+    V, M, W, H = _tiny(81)
+    W2, H2 = nmf64.normalize_components(W, H)
+    assert np.allclose(W2 @ H2, W @ H, rtol=1e-14)
+    assert np.allclose(np.linalg.norm(H2, axis=1), 1.0, rtol=1e-14)
