@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the weighted multiplicative-update NMF hot path on one MI355X.
+
+Workload (STIS-shaped, synthetic): a reference library of N = 500 images of
+200 x 200 px (P = 40000) with a 12 px diagonal occulting wedge and weights
+1/(V + 0.01); a K = 30 basis is built with 1000 iterations of Eq. 3, then 50
+science frames (with injected ring disks at 1e-3) are projected onto it for
+1000 iterations and the model PSF is subtracted.  One step = all of that.
+
+Prints one JSON line.  ``value`` = basis iterations per second of the whole
+step (1000 / step time); the line also carries the GEMM TFLOP/s of the
+fused half-step kernels, projection frames/s, a ``roofline`` object for the
+dominant kernel (timed live with HIP events on the library's stream) and a
+``cpu_baseline`` object (the FP64 oracle on this host's cores).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "NMF iterations/s and GEMM TFLOP/s (% MFMA roofline); projected frames/s to 1e-4 residual"
+PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
+
+K_HRULE, K_WRULE, K_WFINISH, K_OBJ, K_PROJECT, K_SUBTRACT, K_OTHER = range(7)
+K_NAMES = ["hrule", "wrule", "wfinish", "objective", "project", "subtract", "other"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(lib, k, seconds):
+    """The FP64 oracle, untuned, on this host's cores: basis iterations of the
+    same workload until ``seconds`` have elapsed."""
+    from oracle import nmf64, prng
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    except Exception:
+        cores = os.cpu_count() or 1
+    n, p = lib.V.shape
+    Vh, Mw, _ = nmf64.prep(lib.V, lib.M)
+    W = prng.init_matrix(1, prng.MAT_W, n, k)
+    H = prng.init_matrix(1, prng.MAT_H, k, p)
+    t0 = time.perf_counter()
+    it = 0
+    while True:
+        H = nmf64.update_H(Vh, Mw, W, H)
+        W = nmf64.update_W(Vh, Mw, W, H)
+        it += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": it / el, "unit": "iterations/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{it} FP64 basis iterations of the same N={n} P={p} K={k} workload "
+                      f"({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--iters", type=int, default=1000)
+    ap.add_argument("--proj-iters", type=int, default=1000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(frames and pixels would shard across GPUs; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2309_04623_amd import nmf, synth
+
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    nmf.lib()  # fails loudly if the HIP library was not built
+
+    K = 30
+    log("generating the STIS-shaped workload ...")
+    lib = synth.make_cfg2()
+    n, p = lib.V.shape
+    f = lib.T.shape[0]
+    dev = torch.device("cuda:0")
+    V = torch.from_numpy(lib.V).to(dev)
+    M = torch.from_numpy(lib.M).to(dev)
+    T = torch.from_numpy(lib.T).to(dev)
+    MT = torch.from_numpy(lib.MT).to(dev)
+    h = nmf.Handle(0)
+
+    def step():
+        W, H, J, rep = nmf.build_basis(V, M, K, args.iters, precision=args.precision, seed=1,
+                                       handle=h)
+        C, _ = nmf.project(H, T, MT, args.proj_iters, precision=args.precision, seed=2, handle=h)
+        model, resid = nmf.subtract(H, C, T, MT, handle=h)
+        return J, rep
+
+    for i in range(args.warmup):
+        log(f"warmup step {i + 1}/{args.warmup}")
+        step()
+    torch.cuda.synchronize()
+    nmf.profile_enable(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        J, rep = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = {K_NAMES[c]: nmf.profile_get(h, c) for c in range(7)}
+    nmf.profile_enable(h, False)
+    log(f"timed {args.steps} steps: {el:.3f} s; final J {J[-1]:.6e} rel {rep['objective_rel']:.3e}")
+
+    ms_per_step = el * 1e3 / args.steps
+    iters_per_s = args.iters * args.steps / el
+    # algorithmic work of one basis iteration: six N x K x P contractions
+    flops_iter = 12.0 * n * K * p
+    gemm_ms = prof["hrule"][1] + prof["wrule"][1]
+    gemm_tflops = flops_iter * args.iters * args.steps / (gemm_ms * 1e-3) / 1e12
+    basis_ms = sum(prof[c][1] for c in ("hrule", "wrule", "wfinish", "objective"))
+    proj_ms = prof["project"][1] + prof["subtract"][1]
+    frames_per_s = f * args.steps / (proj_ms * 1e-3) if proj_ms > 0 else None
+
+    # Dominant kernel: the fused half-step with the larger summed time.
+    dom = max(("hrule", "wrule"), key=lambda c: prof[c][1])
+    cnt, tot = prof[dom]
+    avg_s = tot * 1e-3 / cnt
+    # per launch: 3 N K P multiply-adds (Y, num, den), and the data stream
+    # (value + weight, 8 B per element) plus the factors read and written
+    flops = 6.0 * n * K * p
+    bytes_ = 8.0 * n * p + 4.0 * (n * K + 2 * K * p) if dom == "hrule" else \
+        8.0 * n * p + 4.0 * (2 * n * K + K * p)
+    peak_fl = PEAK_FP32_TFLOPS if args.precision == "fp32" else PEAK_BF16_TFLOPS / 3
+    t_mfma = flops / (peak_fl * 1e12)
+    t_hbm = bytes_ / (PEAK_HBM_GBS * 1e9)
+    if t_mfma >= t_hbm:
+        roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": peak_fl,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = f"k_dual ({dom} half-step), avg {avg_s * 1e6:.2f} us over {cnt} launches"
+    roof["hbm_GBs_algorithmic"] = bytes_ / avg_s / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": iters_per_s,
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": "STIS-shaped basis build + projection + subtraction",
+                   "images": n, "pixels": p, "image_shape": [200, 200], "k": K,
+                   "basis_iters": args.iters, "frames": f, "proj_iters": args.proj_iters,
+                   "precision": args.precision},
+        "gemm_tflops": gemm_tflops,
+        "basis_iters_per_s_device": args.iters * args.steps / (basis_ms * 1e-3),
+        "frames_per_s": frames_per_s,
+        "kernel_ms_per_step": {c: prof[c][1] / args.steps for c in K_NAMES},
+        "kernel_launches_per_step": {c: prof[c][0] // args.steps for c in K_NAMES},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log(f"timing the FP64 oracle on host cores for ~{args.cpu_seconds:.0f} s ...")
+        out["cpu_baseline"] = cpu_baseline(lib, K, args.cpu_seconds)
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

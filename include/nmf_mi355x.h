@@ -1,0 +1,217 @@
+/*
+ * nmf_mi355x.h -- C ABI of the MI355X (gfx950) weighted multiplicative-update
+ * NMF library: PSF-basis construction from a reference library, projection
+ * of science frames onto the basis (target modelling) and model-PSF
+ * subtraction, after arXiv:2309.04623 ("NMF-based GPU accelerated
+ * coronagraphy pipeline").
+ *
+ * Notation.  The paper factorises its data X ~ W H under weights V (Eq. 1-2).
+ * This library names the data V, the weights M:
+ *     V  : n x p   reference library, one image per row          (float32)
+ *     M  : n x p   per-pixel weight >= 0, 0 = missing / masked   (float32)
+ *     W  : n x k   coefficients                                  (float32)
+ *     H  : k x p   basis components                              (float32)
+ * All matrices are row-major with the last index fastest and tightly
+ * packed (leading dimension = number of columns).
+ *
+ * Pointers.  Every array argument is a DEVICE pointer on the handle's device
+ * unless its comment says [host].  The caller allocates and owns every input
+ * and output; the library never frees them.  Inputs are read-only.  Outputs
+ * may not alias inputs, except W_init == W_out, H_init == H_out and
+ * C_init == C_out (in-place update).
+ *
+ * Streams.  ``stream`` is a hipStream_t passed as void* (NULL = the default
+ * stream).  All work is enqueued on it.  Unless NMF_F_ASYNC is set, calls
+ * synchronise the stream before returning so that data checks and the
+ * report are valid on return.
+ *
+ * Errors.  0 = success, > 0 = warning (outputs valid), < 0 = error (outputs
+ * unspecified).  Argument and shape checks run on the host before anything
+ * is enqueued.  nmf_last_error() returns a thread-local description of the
+ * last failure.  No C++ exception crosses this interface.
+ *
+ * Threading.  A handle owns its device workspace and is not thread-safe; use
+ * one handle per host thread.
+ */
+#ifndef NMF_MI355X_H
+#define NMF_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nmf_handle_s* nmf_handle;
+
+enum nmf_status {
+  NMF_OK = 0,
+  NMF_ERR_ARG = -1,          /* null pointer, bad value, forbidden aliasing   */
+  NMF_ERR_SHAPE = -2,        /* non-positive or inconsistent dimensions       */
+  NMF_ERR_NONFINITE = -3,    /* NaN/Inf data under positive weight           */
+  NMF_ERR_NEGATIVE = -4,     /* negative data under positive weight, or a
+                                negative / non-finite weight                 */
+  NMF_ERR_DIVERGED = -5,     /* objective became non-finite                  */
+  NMF_ERR_HIP = -6,          /* HIP runtime error (text in nmf_last_error)   */
+  NMF_ERR_NOMEM = -7,        /* device workspace allocation failed           */
+  NMF_ERR_UNSUPPORTED = -8,  /* valid request outside what this build runs   */
+  NMF_WARN_NONMONOTONE = 1,  /* objective rose beyond rounding slack         */
+  NMF_WARN_MAXITER = 2       /* tolerance set but not met by max_iter        */
+};
+
+enum nmf_precision {
+  NMF_PREC_FP32 = 0,   /* FP32 operands on FP32 MFMA, FP32 accumulation     */
+  NMF_PREC_BF16X3 = 1  /* split precision: x = x_hi + x_lo (bf16 each, RNE);
+                          a*b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi on bf16 MFMA,
+                          FP32 accumulation                                 */
+};
+
+enum nmf_flags {
+  NMF_F_VALIDATE_DATA = 1,   /* check data/weights, return NMF_ERR_* on bad */
+  NMF_F_CLIP_NEGATIVE = 2,   /* negative data under weight: treat as masked */
+  NMF_F_NORMALIZE_H = 4,     /* unit-L2 basis rows after the build          */
+  NMF_F_BINARY_WEIGHTS = 8,  /* weights are 0/1 (enables bitmask storage)   */
+  NMF_F_MASKED_GRAM = 16,    /* projection through per-frame Gram matrices  */
+  NMF_F_WARM_START = 32,     /* reserved: learned warm start                */
+  NMF_F_ASYNC = 64           /* do not synchronise; report filled later     */
+};
+
+/* Iteration parameters.  Fill with nmf_params_default() first. */
+typedef struct {
+  uint32_t struct_size;  /* = sizeof(nmf_params)                              */
+  int32_t k;             /* number of components, 1 <= k <= min(n, p)        */
+  int32_t max_iter;      /* iterations of Eq. 3 (fixed count when tol == 0)   */
+  int32_t check_every;   /* objective test cadence for tol (0 = never)        */
+  double tol;            /* stop when (J[t-c] - J[t]) / J[t-c] < tol          */
+  uint64_t seed;         /* seed of the counter-based U(0,1) init             */
+  int32_t precision;     /* enum nmf_precision                                */
+  int32_t flags;         /* OR of enum nmf_flags                              */
+  float floor_eps;       /* non-negativity floor applied after each update    */
+  int32_t split;         /* reduction split of the long-axis pass; 0 = auto   */
+} nmf_params;
+
+/* Filled by the calls that iterate.  [host] */
+typedef struct {
+  uint32_t struct_size;  /* = sizeof(nmf_report)                              */
+  int32_t iters_run;     /* iterations performed                              */
+  int32_t status_flags;  /* warnings raised (NMF_WARN_* bit set as 1 << w)    */
+  double objective;      /* final Eq. 2 cost, accumulated in FP64 on device   */
+  double objective_rel;  /* objective / sum(M * V^2)                          */
+  float elapsed_ms;      /* device time of the call's enqueued work           */
+} nmf_report;
+
+/* ---- handle ------------------------------------------------------------ */
+
+/* Create a handle bound to HIP device ``hip_device``. */
+int nmf_create(int hip_device, nmf_handle* out);
+/* Release the handle and its device workspace.  NULL is accepted. */
+int nmf_destroy(nmf_handle h);
+/* Static text for a status code. */
+const char* nmf_status_string(int status);
+/* Thread-local text of the last error raised by this thread. */
+const char* nmf_last_error(void);
+/* Default parameters: floor 1e-30, FP32, 200 iterations, seed 0. [host] */
+void nmf_params_default(nmf_params* prm);
+/* Bytes of device workspace currently held by the handle. */
+size_t nmf_workspace_bytes(nmf_handle h);
+
+/* ---- initialisation ------------------------------------------------------
+ * Random start of W and H (Sec. 2: W and H are initialised randomly).
+ * Fills out[r * cols + c] with the open-interval U(0,1) value of the
+ * counter-based SplitMix64 stream:
+ *   key = mix(seed + (matrix_id + 1) * G),  u = mix(key + (r*cols + c + 1) * G)
+ *   value = ((u >> 41) + 0.5) * 2^-23,    G = 0x9E3779B97F4A7C15,
+ * mix = the SplitMix64 output finaliser (Steele, Lea & Flood 2014).
+ * matrix_id: 0 = W, 1 = H, 2 = projection coefficients.  out: rows x cols.  */
+int nmf_init_uniform(nmf_handle h, uint64_t seed, int32_t matrix_id, int64_t rows,
+                     int64_t cols, float* out, void* stream);
+
+/* ---- objective ------------------------------------------------------------
+ * Eq. 2 weighted Frobenius cost  J = sum_{i,j} M_ij (V_ij - (W H)_ij)^2,
+ * with V_ij taken as 0 wherever M_ij == 0 (masked = missing, Sec. 4.1).
+ * Products in FP32 (or bf16x3), residual squares summed in FP64 in a fixed
+ * order (bitwise reproducible).  J_out: [host] one double.                 */
+int nmf_objective(nmf_handle h, const float* V, const float* M, const float* W,
+                  const float* H, int64_t n, int64_t p, int32_t k, int32_t precision,
+                  double* J_out, void* stream);
+
+/* ---- basis construction --------------------------------------------------
+ * Iterates Eq. 3 (H-rule, then the W-rule with the new H) prm->max_iter
+ * times from (W_init, H_init), or from the seeded U(0,1) init when those are
+ * NULL.  After each update x := max(x, floor_eps); a zero denominator keeps
+ * the factor.  Data under zero weight are ignored whatever their value.
+ *   V, M            : n x p inputs
+ *   W_init, H_init  : nullable n x k and k x p starts
+ *   W_out, H_out    : n x k and k x p results
+ *   obj_hist        : [host] nullable, max_iter + 1 doubles: J before each
+ *                     iteration and after the last one
+ *   rep             : [host] nullable report
+ * Errors: NMF_ERR_ARG/SHAPE before any work; with NMF_F_VALIDATE_DATA,
+ * NMF_ERR_NONFINITE / NMF_ERR_NEGATIVE for bad data under weight;
+ * NMF_ERR_DIVERGED if J turns non-finite.                                  */
+int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int64_t p,
+                    const nmf_params* prm, const float* W_init, const float* H_init,
+                    float* W_out, float* H_out, double* obj_hist, nmf_report* rep,
+                    void* stream);
+
+/* ---- projection (target modelling) ---------------------------------------
+ * Sec. 4.1: the basis models each target frame individually.  With H fixed,
+ * each frame's coefficient row c_f (1 x k) follows Eq. 3's W-rule:
+ *   c_f <- max(c_f o [(m_f o t_f) H^T] / [(m_f o (c_f H)) H^T], floor_eps)
+ * for prm->max_iter iterations, from C_init (nullable: seeded U(0,1) with
+ * matrix_id 2).  With NMF_F_MASKED_GRAM the denominator is formed as
+ * c_f G_f, G_f = H diag(m_f) H^T (same value in exact arithmetic).
+ *   H       : k x p basis;  T, M_T : f x p frames and weights
+ *   C_out   : f x k coefficients
+ *   obj_out : nullable f doubles (device): final per-frame Eq. 2 cost     */
+int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float* T,
+                const float* M_T, int64_t f, const nmf_params* prm, const float* C_init,
+                float* C_out, double* obj_out, nmf_report* rep, void* stream);
+
+/* Same iteration for frames stored as CSR rows: frame i owns entries
+ * offsets[i] .. offsets[i+1]-1 of pix (int32 pixel index in [0, p)),
+ * val (float32 data) and wt (float32 weight; NULL = all ones).  Pixel
+ * indices within a frame must be distinct.  offsets: f + 1 int64, device. */
+int nmf_project_ragged(nmf_handle h, const float* H, int64_t k, int64_t p, int64_t f,
+                       const int64_t* offsets, const int32_t* pix, const float* val,
+                       const float* wt, const nmf_params* prm, const float* C_init,
+                       float* C_out, double* obj_out, nmf_report* rep, void* stream);
+
+/* ---- subtraction -----------------------------------------------------------
+ * Sec. 1 and Sec. 4.1: the model PSF c_f H is removed from each frame:
+ *   model_out[f, j] = sum_k C[f, k] H[k, j]          (every pixel)
+ *   resid_out[f, j] = T[f, j] - s_f * model[f, j]     where M_T[f, j] > 0,
+ *                     NaN                              where M_T[f, j] == 0,
+ * s_f = scale[f] (NULL: 1).  The sum is accumulated in FP64.
+ *   H: k x p; C: f x k; T, M_T: f x p; scale: nullable f; model_out:
+ *   nullable f x p; resid_out: f x p.                                      */
+int nmf_subtract(nmf_handle h, const float* H, const float* C, const float* T,
+                 const float* M_T, int64_t f, int64_t k, int64_t p, const float* scale,
+                 float* model_out, float* resid_out, void* stream);
+
+/* ---- live kernel timing ----------------------------------------------------
+ * Opt-in instrumentation for measurement: while enabled, every kernel the
+ * handle launches is bracketed by two HIP events recorded on the call's
+ * stream, and the elapsed time is summed per kernel class.  Adds two event
+ * records per launch; off by default.                                        */
+enum nmf_kernel_class {
+  NMF_K_HRULE = 0,      /* fused H-rule half-step over V (also yields J)      */
+  NMF_K_WRULE = 1,      /* fused W-rule half-step over V^T (split partials)   */
+  NMF_K_WFINISH = 2,    /* W-rule finish: partial sums + update               */
+  NMF_K_OBJECTIVE = 3,  /* objective-only pass                                */
+  NMF_K_PROJECT = 4,    /* projection iteration kernels                       */
+  NMF_K_SUBTRACT = 5,   /* model-PSF subtraction                              */
+  NMF_K_OTHER = 6,      /* staging, layouts, reductions, init                 */
+  NMF_K_COUNT = 7
+};
+/* Turn timing on (1) or off (0); turning it on clears the counters. */
+int nmf_profile_enable(nmf_handle h, int on);
+/* Launch count and summed device milliseconds of one kernel class
+ * (waits for the recorded events).  count, total_ms: [host].               */
+int nmf_profile_get(nmf_handle h, int32_t kernel_class, int64_t* count, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NMF_MI355X_H */

@@ -1,0 +1,312 @@
+// Streaming kernels around the fused half-step: data staging, factor
+// layouts, the W-rule finish, fixed-order FP64 reductions, seeded init,
+// basis normalisation, model-PSF subtraction and per-frame objectives.
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace nmf {
+
+// ---------------------------------------------------------------------------
+// Staging (masked pixels are missing data: Vhat = V where M > 0, else 0)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_stage(StageArgs a) {
+  __shared__ float tv[32][33];
+  __shared__ float tm[32][33];
+  __shared__ double red[256];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int cb = blockIdx.x * 32, rb = blockIdx.y * 32;
+  int bad = 0;
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = rb + ty + 8 * q, c = cb + tx;
+    float v = 0.f, m = 0.f;
+    if (r < a.n && c < a.p) {
+      v = a.V[(int64_t)r * a.p + c];
+      m = a.M[(int64_t)r * a.p + c];
+      if (!(m >= 0.f) || isinf(m)) {  // negative, NaN or Inf weight
+        bad |= 4;
+        m = 0.f;
+      }
+      if (m > 0.f) {
+        if (!isfinite(v)) {
+          bad |= 1;
+          v = 0.f;
+        } else if (v < 0.f) {
+          if (a.clip_negative) {
+            m = 0.f;
+            v = 0.f;
+          } else {
+            bad |= 2;
+          }
+        }
+      } else {
+        v = 0.f;
+      }
+      acc += (double)m * (double)v * (double)v;
+    }
+    a.D[(int64_t)r * a.p_pad + c] = v;
+    a.Mw[(int64_t)r * a.p_pad + c] = m;
+    tv[ty + 8 * q][tx] = v;
+    tm[ty + 8 * q][tx] = m;
+  }
+  __syncthreads();
+  if (a.DT) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = cb + ty + 8 * q, r = rb + tx;
+      a.DT[(int64_t)c * a.n_pad + r] = tv[tx][ty + 8 * q];
+      a.MwT[(int64_t)c * a.n_pad + r] = tm[tx][ty + 8 * q];
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+  if (bad) atomicOr(a.status, bad);
+}
+
+hipError_t launch_stage(const StageArgs& a, int* nblocks_out, hipStream_t s) {
+  const dim3 g(a.p_pad / 32, a.n_pad / 32);
+  *nblocks_out = g.x * g.y;
+  hipLaunchKernelGGL(k_stage, g, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order FP64 reduction (single block)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce_f64(const double* part, int n, double* out,
+                                                   int* status) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0];
+    if (status && !isfinite(red[0])) atomicOr(status, 8);
+  }
+}
+
+hipError_t launch_reduce_f64(const double* part, int n, double* out, int* status,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, s, part, n, out, status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Seeded init
+// ---------------------------------------------------------------------------
+__global__ void k_init_uniform(uint64_t key, int64_t count, float* out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = sm_uniform(key, (uint64_t)i);
+}
+
+hipError_t launch_init_uniform(uint64_t seed, int matrix_id, int64_t count, float* out,
+                               hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = (count + 255) / 256;
+  hipLaunchKernelGGL(k_init_uniform, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256),
+                     0, s, sm_key(seed, matrix_id), count, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Factor layouts
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void store_layouts(int r, int k, float v, int rows_pad, int KP,
+                                              float* m, __bf16* mh, __bf16* ml, float* t,
+                                              float* tp, __bf16* tph, __bf16* tpl) {
+  __bf16 hi, lo;
+  split_bf16(v, hi, lo);
+  m[(int64_t)r * KP + k] = v;
+  mh[(int64_t)r * KP + k] = hi;
+  ml[(int64_t)r * KP + k] = lo;
+  t[(int64_t)k * rows_pad + r] = v;
+  tp[(int64_t)k * rows_pad + perm_f32(r)] = v;
+  tph[(int64_t)k * rows_pad + perm_bf16(r)] = hi;
+  tpl[(int64_t)k * rows_pad + perm_bf16(r)] = lo;
+}
+
+__global__ __launch_bounds__(256) void k_factor_fill(FactorFillArgs a) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int k = blockIdx.y;
+  if (r >= a.rows_pad) return;
+  float v = 0.f;
+  if (r < a.rows && k < a.K) {
+    const int64_t idx = a.user_is_kxr ? (int64_t)k * a.rows + r : (int64_t)r * a.K + k;
+    v = a.src ? a.src[idx] : sm_uniform(sm_key(a.seed, a.matrix_id), (uint64_t)idx);
+  }
+  store_layouts(r, k, v, a.rows_pad, a.KP, a.m, a.mh, a.ml, a.t, a.tp, a.tph, a.tpl);
+}
+
+hipError_t launch_factor_fill(const FactorFillArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_factor_fill, dim3((a.rows_pad + 255) / 256, a.KP), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_factor_out(const float* t, int rows, int rows_pad, int K,
+                                                   int out_is_kxr, float* out) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int k = blockIdx.y;
+  if (r >= rows) return;
+  const float v = t[(int64_t)k * rows_pad + r];
+  if (out_is_kxr)
+    out[(int64_t)k * rows + r] = v;
+  else
+    out[(int64_t)r * K + k] = v;
+}
+
+hipError_t launch_factor_out(const float* t, int rows, int rows_pad, int K, int KP,
+                             int out_is_kxr, float* out, hipStream_t s) {
+  (void)KP;
+  hipLaunchKernelGGL(k_factor_out, dim3((rows + 255) / 256, K), dim3(256), 0, s, t, rows,
+                     rows_pad, K, out_is_kxr, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// W-rule finish: fixed-order sum over the split partials, then the update
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_row_update(RowUpdateArgs a) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  const int k = blockIdx.y;
+  if (c >= a.C_pad) return;
+  const int64_t stride = (int64_t)a.KP * a.C_pad;
+  const float* pn = a.partial + (int64_t)k * a.C_pad + c;
+  double num = 0.0, den = 0.0;
+  for (int s = 0; s < a.S; ++s) {
+    num += pn[(int64_t)(2 * s) * stride];
+    den += pn[(int64_t)(2 * s + 1) * stride];
+  }
+  float nv = 0.f;
+  if (k < a.K && c < a.C_valid) nv = mu_apply(a.m[(int64_t)c * a.KP + k], (float)num, (float)den, a.eps);
+  a.m[(int64_t)c * a.KP + k] = nv;
+  a.t[(int64_t)k * a.C_pad + c] = nv;
+  if (a.prec == PREC_FP32) {
+    a.tp[(int64_t)k * a.C_pad + perm_f32(c)] = nv;
+  } else {
+    __bf16 hi, lo;
+    split_bf16(nv, hi, lo);
+    a.mh[(int64_t)c * a.KP + k] = hi;
+    a.ml[(int64_t)c * a.KP + k] = lo;
+    a.tph[(int64_t)k * a.C_pad + perm_bf16(c)] = hi;
+    a.tpl[(int64_t)k * a.C_pad + perm_bf16(c)] = lo;
+  }
+}
+
+hipError_t launch_row_update(const RowUpdateArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_update, dim3((a.C_pad + 255) / 256, a.KP), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Basis normalisation: H_k <- H_k / ||H_k||, W[:, k] <- W[:, k] ||H_k||
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_normalize(float* Ht, int p_pad, float* Wt, int n_pad) {
+  __shared__ double red[256];
+  const int k = blockIdx.x;
+  float* hr = Ht + (int64_t)k * p_pad;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < p_pad; i += 256) s += (double)hr[i] * (double)hr[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double d = red[0] > 0.0 ? sqrt(red[0]) : 1.0;
+  for (int i = threadIdx.x; i < p_pad; i += 256) hr[i] = (float)((double)hr[i] / d);
+  float* wr = Wt + (int64_t)k * n_pad;
+  for (int i = threadIdx.x; i < n_pad; i += 256) wr[i] = (float)((double)wr[i] * d);
+}
+
+hipError_t launch_normalize(float* Ht, int KP, int p_pad, int K, float* Wt, int n_pad,
+                            hipStream_t s) {
+  (void)KP;
+  hipLaunchKernelGGL(k_normalize, dim3(K), dim3(256), 0, s, Ht, p_pad, Wt, n_pad);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Subtraction: model = C H (FP64 accumulation), residual = T - s * model,
+// NaN where the frame's weight is 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_subtract(const float* H, const float* C, const float* T,
+                                                 const float* MT, int k, int64_t p,
+                                                 const float* scale, float* model,
+                                                 float* resid) {
+  extern __shared__ float cs[];
+  const int64_t f = blockIdx.y;
+  for (int i = threadIdx.x; i < k; i += 256) cs[i] = C[f * k + i];
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= p) return;
+  double acc = 0.0;
+  for (int i = 0; i < k; ++i) acc = fma((double)cs[i], (double)H[(int64_t)i * p + j], acc);
+  const float mdl = (float)acc;
+  const float sf = scale ? scale[f] : 1.0f;
+  const int64_t o = f * p + j;
+  if (model) model[o] = mdl;
+  const float t = T[o];
+  resid[o] = MT[o] > 0.f ? (float)((double)t - (double)sf * acc) : __builtin_nanf("");
+}
+
+hipError_t launch_subtract(const float* H, const float* C, const float* T, const float* MT,
+                           int64_t f, int k, int64_t p, const float* scale, float* model,
+                           float* resid, hipStream_t s) {
+  const dim3 g((unsigned)((p + 255) / 256), (unsigned)f);
+  hipLaunchKernelGGL(k_subtract, g, dim3(256), k * sizeof(float), s, H, C, T, MT, k, p, scale,
+                     model, resid);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Per-frame objective sum_p m (t - c H)^2 (FP64)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_frame_objective(const float* H, const float* C,
+                                                        const float* T, const float* MT, int k,
+                                                        int64_t p, double* out) {
+  extern __shared__ float cs[];
+  __shared__ double red[256];
+  const int64_t f = blockIdx.x;
+  for (int i = threadIdx.x; i < k; i += 256) cs[i] = C[f * k + i];
+  __syncthreads();
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < p; j += 256) {
+    const float m = MT[f * p + j];
+    if (m > 0.f) {
+      double acc = 0.0;
+      for (int i = 0; i < k; ++i) acc = fma((double)cs[i], (double)H[(int64_t)i * p + j], acc);
+      const double d = (double)T[f * p + j] - acc;
+      s += (double)m * d * d;
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[f] = red[0];
+}
+
+hipError_t launch_frame_objective(const float* H, const float* C, const float* T,
+                                  const float* MT, int64_t f, int k, int64_t p, double* out,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_frame_objective, dim3((unsigned)f), dim3(256), k * sizeof(float), s, H, C,
+                     T, MT, k, p, out);
+  return hipGetLastError();
+}
+
+}  // namespace nmf

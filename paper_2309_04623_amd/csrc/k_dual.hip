@@ -1,0 +1,256 @@
+// Fused multiplicative-update half-step (Eq. 3 of arXiv:2309.04623) for
+// gfx950.
+//
+// One workgroup is one wave and owns a 32-column tile of the data matrix D
+// (R x C) over a range of rows.  For every block of 32 rows it
+//   1. forms Y = L[rows] * Rt[:, cols] on MFMA (the model W H, Eq. 1),
+//   2. reads D and the weights Mw for the same 32x32 tile and forms
+//      A = Mw o D, Z = Mw o Y and the residual term Mw (D - Y)^2 (Eq. 2),
+//   3. accumulates num += L^T A and den += L^T Z on MFMA, with Y, A and Z fed
+//      from the accumulator registers of step 1 without any re-layout: the
+//      32x32 accumulator layout is the B-operand layout of the next 32x32
+//      MFMA up to a fixed permutation of the reduction index, and the L^T
+//      operand is stored with that permutation applied.
+// Y, A and Z never leave registers.
+//
+// Modes:
+//   MODE_UPDATE  the block covers all rows: apply Rt <- max(Rt o num/den, eps)
+//                to its tile and write the layouts the other half-step reads
+//                (H-rule of Eq. 3 on V; also yields J for the current W, H).
+//   MODE_SPLIT   the block covers one chunk of rows: write num/den partials,
+//                finished by the row-update kernel (W-rule, on V^T).
+//   MODE_OBJ     objective only.
+//
+// FP32 products use v_mfma_f32_32x32x2_f32.  The split-precision products
+// use v_mfma_f32_32x32x16_bf16 three times per product (hi*hi + hi*lo +
+// lo*hi), FP32 accumulation.
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace nmf {
+
+template <int PREC, int KP, int MODE>
+__global__ __launch_bounds__(64) void k_dual(DualArgs a) {
+  static_assert(KP % 32 == 0, "KP must be a multiple of 32");
+  constexpr int MT = KP / 32;  // 32-row tiles of the num/den outputs
+  const int lane = threadIdx.x;
+  const int col = lane & 31;
+  const int half = lane >> 5;
+  const int c0 = blockIdx.x * TILE;
+  const int r_begin = blockIdx.y * a.rows_per_split;
+  const int r_end = min(r_begin + a.rows_per_split, a.R_pad);
+
+  // ---- right-factor tile, resident for the whole block ------------------
+  // FP32: product step j uses reduction index half*KP/2 + j.
+  // BF16: product step j uses reduction indices 16j + 8*half + e, e = 0..7.
+  constexpr int NR_F32 = (PREC == PREC_FP32) ? KP / 2 : 1;
+  constexpr int NR_BF = (PREC == PREC_FP32) ? 1 : KP / 16;
+  float rt[NR_F32];
+  bf16x8 rth[NR_BF], rtl[NR_BF];
+  if constexpr (PREC == PREC_FP32) {
+    const float* rp = a.Rt + (int64_t)(half * (KP / 2)) * a.ldr + c0 + col;
+#pragma unroll
+    for (int j = 0; j < KP / 2; ++j) rt[j] = rp[(int64_t)j * a.ldr];
+  } else {
+#pragma unroll
+    for (int j = 0; j < KP / 16; ++j) {
+      const float* rp = a.Rt + (int64_t)(16 * j + 8 * half) * a.ldr + c0 + col;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        __bf16 hi, lo;
+        split_bf16(rp[(int64_t)e * a.ldr], hi, lo);
+        rth[j][e] = hi;
+        rtl[j][e] = lo;
+      }
+    }
+  }
+
+  f32x16 num[MT], den[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    num[t] = zero16();
+    den[t] = zero16();
+  }
+  double jacc = 0.0;
+
+  for (int r0 = r_begin; r0 < r_end; r0 += TILE) {
+    // ---- data tile in accumulator layout --------------------------------
+    float dv[16], mv[16];
+    {
+      const float* dp = a.D + (int64_t)(r0 + 4 * half) * a.ldd + c0 + col;
+      const float* mp = a.Mw + (int64_t)(r0 + 4 * half) * a.ldd + c0 + col;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int64_t off = (int64_t)(8 * (i >> 2) + (i & 3)) * a.ldd;
+        dv[i] = __builtin_nontemporal_load(dp + off);
+        mv[i] = __builtin_nontemporal_load(mp + off);
+      }
+    }
+
+    // ---- Y = L[r0:r0+32, :] * Rt -----------------------------------------
+    f32x16 y = zero16();
+    if constexpr (PREC == PREC_FP32) {
+      const float* lp = a.L + (int64_t)(r0 + col) * KP + half * (KP / 2);
+#pragma unroll
+      for (int j4 = 0; j4 < KP / 2; j4 += 4) {
+        const f32x4 lv = *reinterpret_cast<const f32x4*>(lp + j4);
+        y = mfma_f32(lv[0], rt[j4 + 0], y);
+        y = mfma_f32(lv[1], rt[j4 + 1], y);
+        y = mfma_f32(lv[2], rt[j4 + 2], y);
+        y = mfma_f32(lv[3], rt[j4 + 3], y);
+      }
+    } else {
+      const __bf16* lph = a.Lh + (int64_t)(r0 + col) * KP + 8 * half;
+      const __bf16* lpl = a.Ll + (int64_t)(r0 + col) * KP + 8 * half;
+#pragma unroll
+      for (int j = 0; j < KP / 16; ++j) {
+        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(lph + 16 * j);
+        const bf16x8 al = *reinterpret_cast<const bf16x8*>(lpl + 16 * j);
+        y = mfma_bf16x3(ah, al, rth[j], rtl[j], y);
+      }
+    }
+
+    // ---- elementwise: A = Mw o D, Z = Mw o Y, J += Mw (D - Y)^2 -----------
+    float av[16], zv[16];
+    float js = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      av[i] = mv[i] * dv[i];
+      zv[i] = mv[i] * y[i];
+      if constexpr (MODE != MODE_SPLIT) {
+        const float d = dv[i] - y[i];
+        js = fmaf(mv[i] * d, d, js);
+      }
+    }
+    if constexpr (MODE != MODE_SPLIT) jacc += (double)js;
+
+    if constexpr (MODE != MODE_OBJ) {
+      // ---- num += L^T A, den += L^T Z ------------------------------------
+      if constexpr (PREC == PREC_FP32) {
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          const float* lt = a.LT + (int64_t)(32 * t + col) * a.ldlt + r0 + 16 * half;
+          f32x4 q[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) q[u] = *reinterpret_cast<const f32x4*>(lt + 4 * u);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            num[t] = mfma_f32(q[i >> 2][i & 3], av[i], num[t]);
+            den[t] = mfma_f32(q[i >> 2][i & 3], zv[i], den[t]);
+          }
+        }
+      } else {
+        bf16x8 ah[2], al[2], zh[2], zl[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            __bf16 hi, lo;
+            split_bf16(av[8 * j + e], hi, lo);
+            ah[j][e] = hi;
+            al[j][e] = lo;
+            split_bf16(zv[8 * j + e], hi, lo);
+            zh[j][e] = hi;
+            zl[j][e] = lo;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          const int64_t off = (int64_t)(32 * t + col) * a.ldlt + r0 + 8 * half;
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const bf16x8 lh = *reinterpret_cast<const bf16x8*>(a.LTh + off + 16 * j);
+            const bf16x8 ll = *reinterpret_cast<const bf16x8*>(a.LTl + off + 16 * j);
+            num[t] = mfma_bf16x3(lh, ll, ah[j], al[j], num[t]);
+            den[t] = mfma_bf16x3(lh, ll, zh[j], zl[j], den[t]);
+          }
+        }
+      }
+    }
+  }
+
+  // ---- objective partial (fixed-order wave sum) ---------------------------
+  if constexpr (MODE != MODE_SPLIT) {
+    if (a.Jpart) {
+      const double js = wave_sum(jacc);
+      if (lane == 0) a.Jpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = js;
+    }
+  }
+
+  if constexpr (MODE == MODE_SPLIT) {
+    float* pn = a.partial + (int64_t)blockIdx.y * 2 * KP * a.C_pad;
+    float* pd = pn + (int64_t)KP * a.C_pad;
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int k = 32 * t + acc_row(i, half);
+        pn[(int64_t)k * a.C_pad + c0 + col] = num[t][i];
+        pd[(int64_t)k * a.C_pad + c0 + col] = den[t][i];
+      }
+    }
+  }
+
+  if constexpr (MODE == MODE_UPDATE) {
+    const int c = c0 + col;
+    const bool cval = c < a.C_valid;
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int k = 32 * t + acc_row(i, half);
+        float nv = 0.f;
+        if (cval && k < a.K) nv = mu_apply(a.Rt[(int64_t)k * a.ldr + c], num[t][i], den[t][i], a.eps);
+        a.Rt_out[(int64_t)k * a.ldr + c] = nv;
+        if constexpr (PREC == PREC_FP32) {
+          a.RtT[(int64_t)c * KP + k] = nv;
+          a.Rtp[(int64_t)k * a.ldr + perm_f32(c)] = nv;
+        } else {
+          __bf16 hi, lo;
+          split_bf16(nv, hi, lo);
+          a.RtTh[(int64_t)c * KP + k] = hi;
+          a.RtTl[(int64_t)c * KP + k] = lo;
+          a.Rtph[(int64_t)k * a.ldr + perm_bf16(c)] = hi;
+          a.Rtpl[(int64_t)k * a.ldr + perm_bf16(c)] = lo;
+        }
+      }
+    }
+  }
+}
+
+template <int PREC, int KP>
+static hipError_t launch_kp(int mode, const DualArgs& a, dim3 g, hipStream_t s) {
+  switch (mode) {
+    case MODE_UPDATE:
+      hipLaunchKernelGGL((k_dual<PREC, KP, MODE_UPDATE>), g, dim3(64), 0, s, a);
+      break;
+    case MODE_SPLIT:
+      hipLaunchKernelGGL((k_dual<PREC, KP, MODE_SPLIT>), g, dim3(64), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_dual<PREC, KP, MODE_OBJ>), g, dim3(64), 0, s, a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_prec(int kp, int mode, const DualArgs& a, dim3 g, hipStream_t s) {
+  switch (kp) {
+    case 32: return launch_kp<PREC, 32>(mode, a, g, s);
+    case 64: return launch_kp<PREC, 64>(mode, a, g, s);
+    case 96: return launch_kp<PREC, 96>(mode, a, g, s);
+    case 128: return launch_kp<PREC, 128>(mode, a, g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_dual(int prec, int kp, int mode, const DualArgs& a, int grid_x, int grid_y,
+                       hipStream_t s) {
+  const dim3 g(grid_x, grid_y);
+  if (prec == PREC_FP32) return launch_prec<PREC_FP32>(kp, mode, a, g, s);
+  return launch_prec<PREC_BF16X3>(kp, mode, a, g, s);
+}
+
+}  // namespace nmf

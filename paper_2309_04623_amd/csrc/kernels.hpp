@@ -1,0 +1,135 @@
+// Internal launch interface between the host library (api.cpp) and the
+// gfx950 kernels.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nmf {
+
+// One multiplicative-update half-step over a data matrix D (R x C, stored
+// padded to R_pad x C_pad, row-major) with weights Mw of the same shape:
+//   Y   = L Rt                      (L: R x K rows, Rt: K x C tile)
+//   num = L^T (Mw o D),  den = L^T (Mw o Y)   (reduced over R)
+// and optionally J = sum Mw (D - Y)^2.
+// The H-rule of Eq. 3 is this step on (D = V, L = W, Rt = H); the W-rule is
+// the same step on the transposed problem (D = V^T, L = H^T, Rt = W^T).
+struct DualArgs {
+  const float* D;
+  const float* Mw;
+  int64_t ldd;
+  int R_pad, C_pad, C_valid, rows_per_split;
+  // left factor rows (R_pad x KP): FP32, or the bf16 hi/lo split
+  const float* L;
+  const __bf16* Lh;
+  const __bf16* Ll;
+  // left factor transposed (KP x R_pad), reduction index permuted per 32-block
+  const float* LT;
+  const __bf16* LTh;
+  const __bf16* LTl;
+  int64_t ldlt;
+  // right factor (KP x C_pad, row-major)
+  const float* Rt;
+  int64_t ldr;
+  // outputs
+  float* partial;  // split mode: [split][2][KP][C_pad]
+  double* Jpart;   // per-block objective partial (nullable)
+  // update mode: the new right factor and the layouts the other half-step reads
+  float* Rt_out;   // KP x C_pad (may equal Rt)
+  float* RtT;      // C_pad x KP FP32
+  __bf16* RtTh;    // C_pad x KP bf16 hi
+  __bf16* RtTl;    // C_pad x KP bf16 lo
+  float* Rtp;      // KP x C_pad FP32, permuted (FP32 operand order)
+  __bf16* Rtph;    // KP x C_pad bf16 hi, permuted (bf16 operand order)
+  __bf16* Rtpl;
+  int K;
+  float eps;
+};
+
+enum DualMode { MODE_UPDATE = 0, MODE_SPLIT = 1, MODE_OBJ = 2 };
+
+hipError_t launch_dual(int prec, int kp, int mode, const DualArgs& a, int grid_x, int grid_y,
+                       hipStream_t s);
+
+// Finishes the W-rule: sums split partials (fixed order), applies the update
+// to the factor rows and refreshes every layout of the factor.
+struct RowUpdateArgs {
+  const float* partial;  // [S][2][KP][C_pad]
+  int S, KP, C_pad, C_valid, K;
+  float eps;
+  float* m;          // C_pad x KP master FP32 (updated in place)
+  __bf16* mh;        // C_pad x KP bf16 hi/lo
+  __bf16* ml;
+  float* t;          // KP x C_pad transposed FP32
+  float* tp;         // KP x C_pad transposed, FP32 operand order
+  __bf16* tph;       // KP x C_pad transposed, bf16 operand order
+  __bf16* tpl;
+  int prec;
+};
+hipError_t launch_row_update(const RowUpdateArgs& a, hipStream_t s);
+
+// Layout fill of a factor: from a user matrix (rows x K, row-major, or
+// K x rows if ``user_is_kxr``), or from the seeded generator when src is
+// null, write every internal layout; padding entries are 0.
+struct FactorFillArgs {
+  const float* src;
+  int user_is_kxr;
+  uint64_t seed;
+  int matrix_id;
+  int rows, rows_pad, K, KP;
+  float* m;
+  __bf16* mh;
+  __bf16* ml;
+  float* t;
+  float* tp;
+  __bf16* tph;
+  __bf16* tpl;
+};
+hipError_t launch_factor_fill(const FactorFillArgs& a, hipStream_t s);
+
+// Copy the K x rows block of a transposed layout (KP x rows_pad) out to a user
+// matrix, either rows x K (transpose) or K x rows.
+hipError_t launch_factor_out(const float* t, int rows, int rows_pad, int K, int KP,
+                             int out_is_kxr, float* out, hipStream_t s);
+
+// Data staging: Vhat = V where M > 0 else 0 into padded D and its transpose,
+// weights likewise; flags bad data under positive weight; per-block partial
+// sums of M * Vhat^2.
+struct StageArgs {
+  const float* V;
+  const float* M;
+  int64_t n, p;
+  int n_pad, p_pad;
+  int clip_negative;
+  float* D;    // n_pad x p_pad
+  float* Mw;   // n_pad x p_pad
+  float* DT;   // p_pad x n_pad (nullable)
+  float* MwT;  // p_pad x n_pad (nullable)
+  int* status; // bit 0: non-finite data, bit 1: negative data, bit 2: bad weight
+  double* part;
+};
+hipError_t launch_stage(const StageArgs& a, int* nblocks_out, hipStream_t s);
+
+// Fixed-order FP64 sum of ``n`` partials into out[0] (single block).
+// With ``check``: status |= 8 if the sum is not finite.
+hipError_t launch_reduce_f64(const double* part, int n, double* out, int* status, hipStream_t s);
+
+hipError_t launch_init_uniform(uint64_t seed, int matrix_id, int64_t count, float* out,
+                               hipStream_t s);
+
+// Unit-L2 normalisation of the K basis rows (k x P_pad master plus layouts)
+// with the inverse scale moved into the coefficient rows.
+hipError_t launch_normalize(float* Ht, int KP, int p_pad, int K, float* Wm, int n_pad,
+                            hipStream_t s);
+
+// Subtraction kernel.
+hipError_t launch_subtract(const float* H, const float* C, const float* T, const float* MT,
+                           int64_t f, int k, int64_t p, const float* scale, float* model,
+                           float* resid, hipStream_t s);
+
+// Per-frame objective sum_p m (t - c H)^2 for dense frames.
+hipError_t launch_frame_objective(const float* H, const float* C, const float* T,
+                                  const float* MT, int64_t f, int k, int64_t p, double* out,
+                                  hipStream_t s);
+
+}  // namespace nmf

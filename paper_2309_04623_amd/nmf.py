@@ -1,0 +1,288 @@
+"""Python binding of the gfx950 NMF library (``libnmf_mi355x.so``).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  torch supplies device memory and the current HIP stream.  If
+the library has not been built the calls raise; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import threading
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnmf_mi355x.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "nmf_mi355x.h")
+
+NMF_OK = 0
+NMF_ERR_ARG, NMF_ERR_SHAPE, NMF_ERR_NONFINITE, NMF_ERR_NEGATIVE = -1, -2, -3, -4
+NMF_ERR_DIVERGED, NMF_ERR_HIP, NMF_ERR_NOMEM, NMF_ERR_UNSUPPORTED = -5, -6, -7, -8
+NMF_WARN_NONMONOTONE, NMF_WARN_MAXITER = 1, 2
+
+PREC = {"fp32": 0, "bf16x3": 1}
+F_VALIDATE_DATA, F_CLIP_NEGATIVE, F_NORMALIZE_H = 1, 2, 4
+F_BINARY_WEIGHTS, F_MASKED_GRAM, F_WARM_START, F_ASYNC = 8, 16, 32, 64
+
+MAT_W, MAT_H, MAT_C = 0, 1, 2
+
+
+class NmfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("k", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+        ("check_every", ctypes.c_int32), ("tol", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("precision", ctypes.c_int32), ("flags", ctypes.c_int32), ("floor_eps", ctypes.c_float),
+        ("split", ctypes.c_int32),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("iters_run", ctypes.c_int32),
+        ("status_flags", ctypes.c_int32), ("objective", ctypes.c_double),
+        ("objective_rel", ctypes.c_double), ("elapsed_ms", ctypes.c_float),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}
+
+
+_vp, _i64, _i32, _u64, _dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p
+_SIGS = {
+    "nmf_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "nmf_destroy": (ctypes.c_int, [_vp]),
+    "nmf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "nmf_last_error": (ctypes.c_char_p, []),
+    "nmf_params_default": (None, [ctypes.POINTER(Params)]),
+    "nmf_workspace_bytes": (ctypes.c_size_t, [_vp]),
+    "nmf_init_uniform": (ctypes.c_int, [_vp, _u64, _i32, _i64, _i64, _vp, _vp]),
+    "nmf_objective": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _i32, _i32, _dp, _vp]),
+    "nmf_build_basis": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, ctypes.POINTER(Params), _vp, _vp,
+                                       _vp, _vp, _dp, ctypes.POINTER(Report), _vp]),
+    "nmf_project": (ctypes.c_int, [_vp, _vp, _i64, _i64, _vp, _vp, _i64, ctypes.POINTER(Params),
+                                   _vp, _vp, _vp, ctypes.POINTER(Report), _vp]),
+    "nmf_project_ragged": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp,
+                                          ctypes.POINTER(Params), _vp, _vp, _vp,
+                                          ctypes.POINTER(Report), _vp]),
+    "nmf_subtract": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp]),
+    "nmf_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "nmf_profile_get": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_double)]),
+}
+
+_lib = None
+_lock = threading.Lock()
+
+
+def header_functions(path: str = HEADER) -> list[str]:
+    """Names of the functions the public header declares."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nmf_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib() -> ctypes.CDLL:
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"HIP library not built ({LIB_PATH}); run __graft_entry__.build()")
+            l = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGS.items():
+                fn = getattr(l, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = l
+    return _lib
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        msg = lib().nmf_last_error().decode(errors="replace")
+        raise NmfError(status, msg)
+    return status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, name, dtype=None):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(device):
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Handle:
+    """Owns a library handle (device workspace) on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().nmf_create(device, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().nmf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib().nmf_workspace_bytes(self.h))
+
+
+_handles: dict[int, Handle] = {}
+
+
+def default_handle(device: int = 0) -> Handle:
+    if device not in _handles:
+        _handles[device] = Handle(device)
+    return _handles[device]
+
+
+def make_params(k, iters, precision="fp32", seed=0, flags=0, eps=1e-30, split=0, tol=0.0,
+                check_every=0) -> Params:
+    p = Params()
+    lib().nmf_params_default(ctypes.byref(p))
+    p.k = int(k)
+    p.max_iter = int(iters)
+    p.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+    p.seed = int(seed)
+    p.flags = int(flags)
+    p.floor_eps = float(eps)
+    p.split = int(split)
+    p.tol = float(tol)
+    p.check_every = int(check_every)
+    return p
+
+
+def _new_report() -> Report:
+    r = Report()
+    r.struct_size = ctypes.sizeof(Report)
+    return r
+
+
+# ---------------------------------------------------------------------------
+
+def init_uniform(seed: int, matrix_id: int, rows: int, cols: int, device: int = 0, handle=None):
+    torch = _torch()
+    h = handle or default_handle(device)
+    out = torch.empty((rows, cols), dtype=torch.float32, device=f"cuda:{device}")
+    _check(lib().nmf_init_uniform(h.h, seed, matrix_id, rows, cols, _dev_ptr(out, "out"),
+                                  _stream(device)))
+    return out
+
+
+def objective(V, M, W, H, precision="fp32", handle=None) -> float:
+    torch = _torch()
+    dev = V.device.index or 0
+    h = handle or default_handle(dev)
+    n, p = V.shape
+    k = W.shape[1]
+    out = ctypes.c_double()
+    f32 = torch.float32
+    _check(lib().nmf_objective(h.h, _dev_ptr(V, "V", f32), _dev_ptr(M, "M", f32),
+                               _dev_ptr(W, "W", f32), _dev_ptr(H, "H", f32), n, p, k,
+                               PREC[precision], ctypes.addressof(out), _stream(dev)))
+    return out.value
+
+
+def build_basis(V, M, k, iters, *, precision="fp32", W_init=None, H_init=None, seed=0, flags=0,
+                eps=1e-30, split=0, tol=0.0, check_every=0, handle=None):
+    """Basis construction (Eq. 3 iterated).  Returns (W, H, J history, report)."""
+    torch = _torch()
+    dev = V.device.index or 0
+    h = handle or default_handle(dev)
+    n, p = V.shape
+    f32 = torch.float32
+    W = torch.empty((n, k), dtype=f32, device=V.device)
+    H = torch.empty((k, p), dtype=f32, device=V.device)
+    hist = np.zeros(iters + 1, np.float64)
+    prm = make_params(k, iters, precision, seed, flags, eps, split, tol, check_every)
+    rep = _new_report()
+    st = _check(lib().nmf_build_basis(
+        h.h, _dev_ptr(V, "V", f32), _dev_ptr(M, "M", f32), n, p, ctypes.byref(prm),
+        _dev_ptr(W_init, "W_init", f32), _dev_ptr(H_init, "H_init", f32), _dev_ptr(W, "W_out"),
+        _dev_ptr(H, "H_out"), hist.ctypes.data, ctypes.byref(rep), _stream(dev)))
+    info = rep.as_dict()
+    info["status"] = st
+    return W, H, hist[: rep.iters_run + 1], info
+
+
+def project(H, T, MT, iters, *, C_init=None, precision="fp32", seed=0, flags=0, eps=1e-30,
+            split=0, want_objective=False, handle=None):
+    """Target modelling: per-frame coefficients with the basis fixed."""
+    torch = _torch()
+    dev = H.device.index or 0
+    h = handle or default_handle(dev)
+    k, p = H.shape
+    f = T.shape[0]
+    f32 = torch.float32
+    C = torch.empty((f, k), dtype=f32, device=H.device)
+    obj = torch.empty(f, dtype=torch.float64, device=H.device) if want_objective else None
+    prm = make_params(k, iters, precision, seed, flags, eps, split)
+    rep = _new_report()
+    _check(lib().nmf_project(h.h, _dev_ptr(H, "H", f32), k, p, _dev_ptr(T, "T", f32),
+                             _dev_ptr(MT, "M_T", f32), f, ctypes.byref(prm),
+                             _dev_ptr(C_init, "C_init", f32), _dev_ptr(C, "C_out"),
+                             _dev_ptr(obj, "obj_out"), ctypes.byref(rep), _stream(dev)))
+    return (C, obj, rep.as_dict()) if want_objective else (C, rep.as_dict())
+
+
+def subtract(H, C, T, MT, scale=None, want_model=True, handle=None):
+    """Model PSF and residual frames (NaN at masked pixels)."""
+    torch = _torch()
+    dev = H.device.index or 0
+    h = handle or default_handle(dev)
+    k, p = H.shape
+    f = T.shape[0]
+    f32 = torch.float32
+    resid = torch.empty((f, p), dtype=f32, device=H.device)
+    model = torch.empty((f, p), dtype=f32, device=H.device) if want_model else None
+    _check(lib().nmf_subtract(h.h, _dev_ptr(H, "H", f32), _dev_ptr(C, "C", f32),
+                              _dev_ptr(T, "T", f32), _dev_ptr(MT, "M_T", f32), f, k, p,
+                              _dev_ptr(scale, "scale", f32), _dev_ptr(model, "model_out"),
+                              _dev_ptr(resid, "resid_out"), _stream(dev)))
+    return model, resid
+
+
+def profile_enable(handle: Handle, on: bool = True):
+    """Live kernel timing (HIP events around each launch) on or off."""
+    _check(lib().nmf_profile_enable(handle.h, 1 if on else 0))
+
+
+def profile_get(handle: Handle, kernel_class: int):
+    """(launch count, summed device ms) of one kernel class."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(lib().nmf_profile_get(handle.h, kernel_class, ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)

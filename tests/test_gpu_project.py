@@ -1,0 +1,95 @@
+"""GPU parity of target modelling (projection with the basis fixed) and of
+model-PSF subtraction against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import nmf64, nnls, prng
+from paper_2309_04623_amd import nmf, synth
+from tests.helpers import dev, host, rel_model_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _basis(k, p, seed=0):
+    g = np.random.default_rng(seed)
+    return (g.gamma(1.0, 1.0, (k, p)) * g.uniform(0.2, 1.0, (k, 1))).astype(np.float32)
+
+
+def _frames(H, f, seed=1, mask_frac=0.1):
+    g = np.random.default_rng(seed)
+    k, p = H.shape
+    T = g.gamma(2.0, 1.0, (f, k)) @ H + np.abs(g.normal(0, 0.05, (f, p)))
+    MT = (g.random((f, p)) >= mask_frac) / (T + 0.01)
+    return T.astype(np.float32), MT.astype(np.float32)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("f,k,p,iters", [(1, 8, 4096, 200), (50, 30, 6400, 300), (37, 5, 1000, 100),
+                                         (3, 100, 3000, 80), (70, 33, 777, 120)])
+def test_projection_parity(f, k, p, iters, precision):
+    H = _basis(k, p, seed=k)
+    T, MT = _frames(H, f, seed=f + k)
+    C0 = prng.init_matrix(5, prng.MAT_C, f, k)
+    say("project", f, k, p, iters, precision)
+    C, obj, _ = nmf.project(dev(H), dev(T), dev(MT), iters, precision=precision, seed=5,
+                            want_objective=True)
+    Cg = host(C)
+    Co = nmf64.project(T, MT, H, C0, iters)
+    Jo = nmf64.frame_objective(T, MT, H, Co)
+    Jg = nmf64.frame_objective(T, MT, H, Cg)
+    tol_j, tol_m = (1e-5, 1e-4) if precision == "fp32" else (1e-4, 1e-3)
+    relJ = np.max(np.abs(Jg - Jo) / Jo)
+    worst = max(rel_model_err(MT[i:i + 1], Cg[i:i + 1] @ H, Co[i:i + 1] @ H) for i in range(f))
+    print(f"  relJ={relJ:.3e} model={worst:.3e}", flush=True)
+    assert relJ <= tol_j and worst <= tol_m
+    assert np.all(Cg >= 0)
+    # the device objective matches the FP64 cost of the returned coefficients
+    assert np.max(np.abs(host(obj) - Jg) / Jg) < 1e-6
+
+
+def test_projection_converges_to_nnls():
+    """Run long enough and the projection reaches the exact weighted NNLS
+    minimiser (brute force over supports, K = 4)."""
+    H = _basis(4, 500, seed=3)
+    T, MT = _frames(H, 6, seed=4)
+    say("project->nnls")
+    C, _ = nmf.project(dev(H), dev(T), dev(MT), 20000, seed=2)
+    C = host(C)
+    for i in range(6):
+        G, b, c = nnls.normal_equations(H, T[i], MT[i])
+        w, j = nnls.nnls_bruteforce(G, b, c)
+        assert nnls.cost(G, b, c, C[i]) - j <= 1e-5 * j
+
+
+def test_cfg2_projection_full_size():
+    """50 STIS-shaped science frames (200x200 px, disks at 1e-3) projected on a
+    30-component basis for 1000 iterations."""
+    lib = synth.make_cfg2(n=60, frames=50)
+    H = np.abs(lib.H0[:30]).astype(np.float32)
+    say("cfg2 projection 50 frames")
+    C, _ = nmf.project(dev(H), dev(lib.T), dev(lib.MT), 1000, seed=8)
+    Cg = host(C)
+    C0 = prng.init_matrix(8, prng.MAT_C, 50, 30)
+    sel = [0, 17, 49]
+    Co = nmf64.project(lib.T[sel], lib.MT[sel], H, C0[sel], 1000)
+    for j, i in enumerate(sel):
+        assert rel_model_err(lib.MT[i:i + 1], Cg[i:i + 1] @ H, Co[j:j + 1] @ H) <= 1e-4
+
+
+@pytest.mark.parametrize("f,k,p", [(1, 8, 4096), (50, 30, 40000), (7, 100, 1001)])
+def test_subtract_parity(f, k, p):
+    g = np.random.default_rng(f + k)
+    H = g.gamma(1.0, 1.0, (k, p)).astype(np.float32)
+    C = g.gamma(2.0, 1.0, (f, k)).astype(np.float32)
+    T = (C.astype(np.float64) @ H + g.normal(0, 0.1, (f, p))).astype(np.float32)
+    MT = (g.random((f, p)) > 0.1).astype(np.float32)
+    T[MT == 0] = np.nan  # masked pixels may hold anything
+    scale = g.uniform(0.5, 1.5, f).astype(np.float32)
+    say("subtract", f, k, p)
+    model, resid = nmf.subtract(dev(H), dev(C), dev(T), dev(MT), scale=dev(scale))
+    mo, ro = nmf64.subtract(T, MT, H, C, scale=scale)
+    mg, rg = host(model), host(resid)
+    assert np.max(np.abs(mg - mo) / np.abs(mo)) < 1e-7
+    assert np.array_equal(np.isnan(rg), np.isnan(ro))
+    ok = ~np.isnan(ro)
+    assert np.max(np.abs(rg[ok] - ro[ok]) / (np.abs(mo[ok]) + np.abs(T[ok]))) < 1e-7
