@@ -88,7 +88,9 @@ typedef struct {
   int32_t precision;     /* enum nmf_precision                                */
   int32_t flags;         /* OR of enum nmf_flags                              */
   float floor_eps;       /* non-negativity floor applied after each update    */
-  int32_t split;         /* reduction split of the long-axis pass; 0 = auto   */
+  int32_t split;         /* row chunks of the split half-step; 0 = auto      */
+  int32_t waves;         /* waves per workgroup of the fused passes (1, 2, 4);
+                            0 = auto                                          */
 } nmf_params;
 
 /* Filled by the calls that iterate.  [host] */

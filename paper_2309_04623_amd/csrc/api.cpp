@@ -233,6 +233,8 @@ int check_params(const nmf_params* prm, int64_t rows, int64_t cols, bool need_k_
   if (!(prm->floor_eps >= 0.f) || !std::isfinite(prm->floor_eps))
     return fail(NMF_ERR_ARG, "floor_eps must be finite and >= 0");
   if (prm->split < 0) return fail(NMF_ERR_ARG, "split must be >= 0");
+  if (prm->waves != 0 && prm->waves != 1 && prm->waves != 2 && prm->waves != 4)
+    return fail(NMF_ERR_ARG, "waves must be 0, 1, 2 or 4");
   return NMF_OK;
 }
 
@@ -299,6 +301,7 @@ void nmf_params_default(nmf_params* prm) {
   prm->flags = 0;
   prm->floor_eps = 1e-30f;
   prm->split = 0;
+  prm->waves = 0;
 }
 
 int nmf_create(int hip_device, nmf_handle* out) {
@@ -358,7 +361,102 @@ int nmf_init_uniform(nmf_handle h, uint64_t seed, int32_t matrix_id, int64_t row
   return NMF_OK;
 }
 
+}  // extern "C"
+
 // ---------------------------------------------------------------------------
+namespace {
+
+// Launch shape of one fused half-step: waves per workgroup and the number of
+// row chunks (grid y).
+struct PassCfg {
+  int nw = 1;
+  int splits = 1;
+  int tiles_per_split = 1;
+};
+
+// Resident waves per SIMD of the fused kernels by padded component count
+// (from their register use).
+int occupancy_for(int KP) { return KP <= 64 ? 2 : 1; }
+constexpr int SIMDS = 1024;  // 256 compute units x 4
+
+PassCfg cfg_whole(int col_tiles, int RT, int KP, int req_nw) {
+  PassCfg c;
+  const int cap = SIMDS * occupancy_for(KP);
+  c.nw = 1;
+  if (req_nw > 0) {
+    c.nw = req_nw;
+  } else {
+    for (int nw : {4, 2}) {
+      if ((int64_t)col_tiles * nw <= cap && RT >= nw) {
+        c.nw = nw;
+        break;
+      }
+    }
+  }
+  c.splits = 1;
+  c.tiles_per_split = RT;
+  return c;
+}
+
+PassCfg cfg_split(int col_tiles, int RT, int KP, int req_split, int req_nw) {
+  PassCfg c;
+  c.nw = req_nw > 0 ? req_nw : 4;
+  const int cap = SIMDS * occupancy_for(KP);
+  int S = req_split > 0 ? req_split : std::max(1, cap / std::max(1, col_tiles * c.nw));
+  S = std::min(S, std::max(1, RT / c.nw));
+  c.tiles_per_split = (RT + S - 1) / S;
+  c.splits = (RT + c.tiles_per_split - 1) / c.tiles_per_split;
+  return c;
+}
+
+DualArgs pass_args(const float* D, const float* Mw, int RT, int C_pad, int C_valid, const Factor& L,
+                   const float* Rt, int K, float eps) {
+  DualArgs a{};
+  a.D = D;
+  a.Mw = Mw;
+  a.RT = RT;
+  a.tiles_per_split = RT;
+  a.C_pad = C_pad;
+  a.C_valid = C_valid;
+  a.L = L.m;
+  a.Lh = L.mh;
+  a.Ll = L.ml;
+  a.LT = L.tp;
+  a.LTh = L.tph;
+  a.LTl = L.tpl;
+  a.ldlt = L.rows_pad;
+  a.Rt = Rt;
+  a.ldr = C_pad;
+  a.K = K;
+  a.eps = eps;
+  return a;
+}
+
+FinishArgs finish_args(const float* partial, int S, const Factor& f, int C_valid, int K,
+                       float eps, int prec) {
+  FinishArgs a{};
+  a.partial = partial;
+  a.S = S;
+  a.KP = f.KP;
+  a.C_pad = f.rows_pad;
+  a.C_valid = C_valid;
+  a.K = K;
+  a.eps = eps;
+  a.prec = prec;
+  a.m = f.m;
+  a.mh = f.mh;
+  a.ml = f.ml;
+  a.t = f.t;
+  a.tp = f.tp;
+  a.tph = f.tph;
+  a.tpl = f.tpl;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
 int nmf_objective(nmf_handle h, const float* V, const float* M, const float* W, const float* H,
                   int64_t n, int64_t p, int32_t k, int32_t precision, double* J_out,
                   void* stream) {
@@ -378,35 +476,23 @@ int nmf_objective(nmf_handle h, const float* V, const float* M, const float* W, 
   double *part, *Jdev;
   int* stat;
   Factor Wf, Hf;
+  const int nblk = std::max((n_pad / 32) * (p_pad / 32), p_pad / 32);
   if ((rc = ws(h, "D", (size_t)n_pad * p_pad, &D)) || (rc = ws(h, "Mw", (size_t)n_pad * p_pad, &Mw)) ||
       (rc = ws(h, "stat", 1, &stat)) || (rc = ws(h, "Jdev", 2, &Jdev)) ||
+      (rc = ws(h, "part", (size_t)nblk, &part)) ||
       (rc = factor_alloc(h, "W", (int)n, n_pad, KP, &Wf)) ||
       (rc = factor_alloc(h, "H", (int)p, p_pad, KP, &Hf)))
     return rc;
-  const int nblk = std::max((n_pad / 32) * (p_pad / 32), p_pad / 32);
-  if ((rc = ws(h, "part", (size_t)nblk, &part))) return rc;
   HIP_TRY(hipMemsetAsync(stat, 0, sizeof(int), s));
   StageArgs sa{V, M, n, p, n_pad, p_pad, 0, D, Mw, nullptr, nullptr, stat, part};
   int sblocks = 0;
   LAUNCH(NMF_K_OTHER, launch_stage(sa, &sblocks, s));
   LAUNCH(NMF_K_OTHER, launch_factor_fill(fill_args(Wf, W, 0, 0, 0, k), s));
   LAUNCH(NMF_K_OTHER, launch_factor_fill(fill_args(Hf, H, 1, 0, 1, k), s));
-  DualArgs a{};
-  a.D = D;
-  a.Mw = Mw;
-  a.ldd = p_pad;
-  a.R_pad = n_pad;
-  a.C_pad = p_pad;
-  a.C_valid = (int)p;
-  a.rows_per_split = n_pad;
-  a.L = Wf.m;
-  a.Lh = Wf.mh;
-  a.Ll = Wf.ml;
-  a.Rt = Hf.t;
-  a.ldr = p_pad;
+  DualArgs a = pass_args(D, Mw, n_pad / 32, p_pad, (int)p, Wf, Hf.t, k, 0.f);
   a.Jpart = part;
-  a.K = k;
-  LAUNCH(NMF_K_OBJECTIVE, launch_dual(precision, KP, MODE_OBJ, a, p_pad / 32, 1, s));
+  const PassCfg pc = cfg_whole(p_pad / 32, n_pad / 32, KP, 0);
+  LAUNCH(NMF_K_OBJECTIVE, launch_dual(precision, KP, MODE_OBJ, pc.nw, a, p_pad / 32, 1, s));
   LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, p_pad / 32, Jdev, nullptr, s));
   int st = 0;
   HIP_TRY(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -434,31 +520,31 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   const int K = prm->k;
   const int KP = kp_for(K);
   if (KP > KP_MAX) return fail(NMF_ERR_UNSUPPORTED, "k > 128 is not supported by this build");
+  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
   const int T = prm->max_iter;
   const int prec = prm->precision;
   const float eps = prm->floor_eps;
-  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
   DeviceGuard g(h->device);
   if (!g.ok) return fail(NMF_ERR_HIP, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
 
   const int n_pad = round_up(n, 32), p_pad = round_up(p, 32);
-  const int col_tiles_b = n_pad / 32;
-  const int S = auto_split(col_tiles_b, p_pad, prm->split);
-  const int rps = round_up((p_pad + S - 1) / S, 32);
-  const int S_eff = (p_pad + rps - 1) / rps;
+  const int ntile = n_pad / 32, ptile = p_pad / 32;
+  const PassCfg ca = cfg_whole(ptile, ntile, KP, prm->waves);
+  const PassCfg cb = cfg_split(ntile, ptile, KP, prm->split, prm->waves);
 
   float *D, *Mw, *DT, *MwT, *partial;
   double *part, *Jhist, *sum_mv2;
-  int* stat;
+  int *stat, *iter;
   Factor Wf, Hf;
   const size_t nel = (size_t)n_pad * p_pad;
-  const int nblk = std::max((n_pad / 32) * (p_pad / 32), p_pad / 32);
+  const int nblk = std::max(ntile * ptile, ptile);
   if ((rc = ws(h, "D", nel, &D)) || (rc = ws(h, "Mw", nel, &Mw)) || (rc = ws(h, "DT", nel, &DT)) ||
       (rc = ws(h, "MwT", nel, &MwT)) ||
-      (rc = ws(h, "partial", (size_t)S_eff * 2 * KP * n_pad, &partial)) ||
+      (rc = ws(h, "partial", (size_t)cb.splits * 2 * KP * n_pad, &partial)) ||
       (rc = ws(h, "part", (size_t)nblk, &part)) || (rc = ws(h, "Jhist", (size_t)T + 2, &Jhist)) ||
       (rc = ws(h, "summv2", 1, &sum_mv2)) || (rc = ws(h, "stat", 1, &stat)) ||
+      (rc = ws(h, "iter", 1, &iter)) ||
       (rc = factor_alloc(h, "W", (int)n, n_pad, KP, &Wf)) ||
       (rc = factor_alloc(h, "H", (int)p, p_pad, KP, &Hf)))
     return rc;
@@ -467,6 +553,7 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
 
   HIP_TRY(hipEventRecord(h->ev0, s));
   HIP_TRY(hipMemsetAsync(stat, 0, sizeof(int), s));
+  LAUNCH(NMF_K_OTHER, launch_set_int(iter, 0, s));
   StageArgs sa{V, M, n, p, n_pad, p_pad, (prm->flags & NMF_F_CLIP_NEGATIVE) ? 1 : 0,
                D, Mw, DT, MwT, stat, part};
   int sblocks = 0;
@@ -479,28 +566,11 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
     int st = 0;
     HIP_TRY(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-  HIP_TRY(prof_drain(h));
     if ((rc = status_from_stage(st))) return rc;
   }
 
-  // Pass A: H-rule over V (one block per 32-pixel tile, all images).
-  DualArgs A{};
-  A.D = D;
-  A.Mw = Mw;
-  A.ldd = p_pad;
-  A.R_pad = n_pad;
-  A.C_pad = p_pad;
-  A.C_valid = (int)p;
-  A.rows_per_split = n_pad;
-  A.L = Wf.m;
-  A.Lh = Wf.mh;
-  A.Ll = Wf.ml;
-  A.LT = Wf.tp;
-  A.LTh = Wf.tph;
-  A.LTl = Wf.tpl;
-  A.ldlt = n_pad;
-  A.Rt = Hf.t;
-  A.ldr = p_pad;
+  // H-rule over V: one workgroup per 32-pixel tile, all images.
+  DualArgs A = pass_args(D, Mw, ntile, p_pad, (int)p, Wf, Hf.t, K, eps);
   A.Jpart = part;
   A.Rt_out = Hf.t;
   A.RtT = Hf.m;
@@ -509,31 +579,16 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   A.Rtp = Hf.tp;
   A.Rtph = Hf.tph;
   A.Rtpl = Hf.tpl;
-  A.K = K;
-  A.eps = eps;
-  // Pass B: W-rule over V^T (blocks of 32 images x chunks of pixels).
-  DualArgs B{};
-  B.D = DT;
-  B.Mw = MwT;
-  B.ldd = n_pad;
-  B.R_pad = p_pad;
-  B.C_pad = n_pad;
-  B.C_valid = (int)n;
-  B.rows_per_split = rps;
-  B.L = Hf.m;
-  B.Lh = Hf.mh;
-  B.Ll = Hf.ml;
-  B.LT = Hf.tp;
-  B.LTh = Hf.tph;
-  B.LTl = Hf.tpl;
-  B.ldlt = p_pad;
-  B.Rt = Wf.t;
-  B.ldr = n_pad;
+  // W-rule over V^T: 32-image tiles x chunks of pixel tiles, then the finish.
+  DualArgs B = pass_args(DT, MwT, ptile, n_pad, (int)n, Hf, Wf.t, K, eps);
+  B.tiles_per_split = cb.tiles_per_split;
   B.partial = partial;
-  B.K = K;
-  B.eps = eps;
-  RowUpdateArgs U{partial, S_eff, KP, n_pad, (int)n, K, eps, Wf.m, Wf.mh, Wf.ml,
-                  Wf.t, Wf.tp, Wf.tph, Wf.tpl, prec};
+  FinishArgs F = finish_args(partial, cb.splits, Wf, (int)n, K, eps, prec);
+  F.Jpart = part;
+  F.nJ = ptile;
+  F.Jhist = Jhist;
+  F.iter = iter;
+  F.status = stat;
 
   const int c = (prm->tol > 0.0 && prm->check_every > 0) ? prm->check_every : 0;
   int t = 0;
@@ -544,14 +599,13 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   while (t < T) {
     const int chunk_end = c ? std::min(T, t + c) : T;
     for (; t < chunk_end; ++t) {
-      LAUNCH(NMF_K_HRULE, launch_dual(prec, KP, MODE_UPDATE, A, p_pad / 32, 1, s));
-      LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, p_pad / 32, Jhist + t, stat, s));
-      LAUNCH(NMF_K_WRULE, launch_dual(prec, KP, MODE_SPLIT, B, n_pad / 32, S_eff, s));
-      LAUNCH(NMF_K_WFINISH, launch_row_update(U, s));
+      LAUNCH(NMF_K_HRULE, launch_dual(prec, KP, MODE_UPDATE, ca.nw, A, ptile, 1, s));
+      LAUNCH(NMF_K_WRULE, launch_dual(prec, KP, MODE_SPLIT, cb.nw, B, ntile, cb.splits, s));
+      LAUNCH(NMF_K_WFINISH, launch_finish(F, s));
     }
     if (!c) break;
-    // The J of iteration t-1 is known once this chunk completes; decide on the
-    // previous chunk's value so that one chunk stays queued on the device.
+    // J of the last iteration of a chunk is known once that chunk completes;
+    // decide on the previous chunk's value so that one chunk stays queued.
     if (pending_check >= 0) {
       HIP_TRY(hipEventSynchronize(chk));
       const int t1 = pending_check;
@@ -564,7 +618,7 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
         }
       }
     }
-    HIP_TRY(hipMemcpyAsync(hostJ + (t - 1) - 0, Jhist + (t - 1), sizeof(double),
+    HIP_TRY(hipMemcpyAsync(hostJ + (t - 1), Jhist + (t - 1), sizeof(double),
                            hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(chk, s));
     pending_check = t - 1;
@@ -575,9 +629,8 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   }
   const int iters_run = t;
   // Objective after the last iteration.
-  DualArgs O = A;
-  LAUNCH(NMF_K_OBJECTIVE, launch_dual(prec, KP, MODE_OBJ, O, p_pad / 32, 1, s));
-  LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, p_pad / 32, Jhist + iters_run, stat, s));
+  LAUNCH(NMF_K_OBJECTIVE, launch_dual(prec, KP, MODE_OBJ, ca.nw, A, ptile, 1, s));
+  LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, ptile, Jhist + iters_run, stat, s));
   if (prm->flags & NMF_F_NORMALIZE_H) LAUNCH(NMF_K_OTHER, launch_normalize(Hf.t, KP, p_pad, K, Wf.t, n_pad, s));
   LAUNCH(NMF_K_OTHER, launch_factor_out(Wf.t, (int)n, n_pad, K, KP, 0, W_out, s));
   LAUNCH(NMF_K_OTHER, launch_factor_out(Hf.t, (int)p, p_pad, K, KP, 1, H_out, s));
@@ -642,30 +695,28 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
   if (KP > KP_MAX) return fail(NMF_ERR_UNSUPPORTED, "k > 128 is not supported by this build");
   if (prm->flags & NMF_F_MASKED_GRAM)
     return fail(NMF_ERR_UNSUPPORTED, "masked-Gram projection is not available in this build");
-  const int prec = prm->precision;
   if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+  const int prec = prm->precision;
   DeviceGuard g(h->device);
   hipStream_t s = (hipStream_t)stream;
   const int f_pad = round_up(f, 32), p_pad = round_up(p, 32);
-  const int S = auto_split(f_pad / 32, p_pad, prm->split);
-  const int rps = round_up((p_pad + S - 1) / S, 32);
-  const int S_eff = (p_pad + rps - 1) / rps;
-  float *DT, *MwT, *partial, *D, *Mw;
+  const int ftile = f_pad / 32, ptile = p_pad / 32;
+  const PassCfg cb = cfg_split(ftile, ptile, KP, prm->split, prm->waves);
+  float *DT, *MwT, *partial;
   double* part;
   int* stat;
   Factor Cf, Hf;
   const size_t nel = (size_t)f_pad * p_pad;
-  if ((rc = ws(h, "pD", nel, &D)) || (rc = ws(h, "pMw", nel, &Mw)) || (rc = ws(h, "pDT", nel, &DT)) ||
-      (rc = ws(h, "pMwT", nel, &MwT)) ||
-      (rc = ws(h, "ppartial", (size_t)S_eff * 2 * KP * f_pad, &partial)) ||
-      (rc = ws(h, "ppart", (size_t)(f_pad / 32) * (p_pad / 32), &part)) ||
+  if ((rc = ws(h, "pDT", nel, &DT)) || (rc = ws(h, "pMwT", nel, &MwT)) ||
+      (rc = ws(h, "ppartial", (size_t)cb.splits * 2 * KP * f_pad, &partial)) ||
+      (rc = ws(h, "ppart", (size_t)ftile * ptile, &part)) ||
       (rc = ws(h, "stat", 1, &stat)) || (rc = factor_alloc(h, "C", (int)f, f_pad, KP, &Cf)) ||
       (rc = factor_alloc(h, "PH", (int)p, p_pad, KP, &Hf)))
     return rc;
   HIP_TRY(hipEventRecord(h->ev0, s));
   HIP_TRY(hipMemsetAsync(stat, 0, sizeof(int), s));
   StageArgs sa{T, M_T, f, p, f_pad, p_pad, (prm->flags & NMF_F_CLIP_NEGATIVE) ? 1 : 0,
-               D, Mw, DT, MwT, stat, part};
+               nullptr, nullptr, DT, MwT, stat, part};
   int sblocks = 0;
   LAUNCH(NMF_K_OTHER, launch_stage(sa, &sblocks, s));
   LAUNCH(NMF_K_OTHER, launch_factor_fill(fill_args(Hf, H, 1, 0, 1, K), s));
@@ -674,34 +725,15 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
     int st = 0;
     HIP_TRY(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-  HIP_TRY(prof_drain(h));
     if ((rc = status_from_stage(st))) return rc;
   }
-  DualArgs B{};
-  B.D = DT;
-  B.Mw = MwT;
-  B.ldd = f_pad;
-  B.R_pad = p_pad;
-  B.C_pad = f_pad;
-  B.C_valid = (int)f;
-  B.rows_per_split = rps;
-  B.L = Hf.m;
-  B.Lh = Hf.mh;
-  B.Ll = Hf.ml;
-  B.LT = Hf.tp;
-  B.LTh = Hf.tph;
-  B.LTl = Hf.tpl;
-  B.ldlt = p_pad;
-  B.Rt = Cf.t;
-  B.ldr = f_pad;
+  DualArgs B = pass_args(DT, MwT, ptile, f_pad, (int)f, Hf, Cf.t, K, prm->floor_eps);
+  B.tiles_per_split = cb.tiles_per_split;
   B.partial = partial;
-  B.K = K;
-  B.eps = prm->floor_eps;
-  RowUpdateArgs U{partial, S_eff, KP, f_pad, (int)f, K, prm->floor_eps, Cf.m, Cf.mh, Cf.ml,
-                  Cf.t, Cf.tp, Cf.tph, Cf.tpl, prec};
+  FinishArgs F = finish_args(partial, cb.splits, Cf, (int)f, K, prm->floor_eps, prec);
   for (int it = 0; it < prm->max_iter; ++it) {
-    LAUNCH(NMF_K_PROJECT, launch_dual(prec, KP, MODE_SPLIT, B, f_pad / 32, S_eff, s));
-    LAUNCH(NMF_K_PROJECT, launch_row_update(U, s));
+    LAUNCH(NMF_K_PROJECT, launch_dual(prec, KP, MODE_SPLIT, cb.nw, B, ftile, cb.splits, s));
+    LAUNCH(NMF_K_PROJECT, launch_finish(F, s));
   }
   LAUNCH(NMF_K_OTHER, launch_factor_out(Cf.t, (int)f, f_pad, K, KP, 0, C_out, s));
   if (obj_out) LAUNCH(NMF_K_OTHER, launch_frame_objective(H, C_out, T, M_T, f, K, p, obj_out, s));

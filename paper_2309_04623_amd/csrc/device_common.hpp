@@ -120,4 +120,11 @@ __device__ __forceinline__ float mu_apply(float old, float num, float den, float
   return (r > eps || r != r) ? r : eps;  // a NaN propagates to the objective check
 }
 
+__device__ __forceinline__ float mu_apply_d(float old, double num, double den, float eps) {
+  double v = den > 0.0 ? (double)old * num / den : (double)old;
+  if (v > 3.4028234663852886e38) v = 3.4028234663852886e38;
+  const float r = (float)v;
+  return (r > eps || r != r) ? r : eps;
+}
+
 }  // namespace nmf

@@ -10,6 +10,13 @@ namespace nmf {
 // ---------------------------------------------------------------------------
 // Staging (masked pixels are missing data: Vhat = V where M > 0, else 0)
 // ---------------------------------------------------------------------------
+// Offset of element (r, c) of a 32x32 tile in MFMA accumulator order.
+__device__ __forceinline__ int tile_slot_rc(int r, int c) {
+  const int h = (r >> 2) & 1;
+  const int i = ((r >> 3) << 2) | (r & 3);
+  return (c + 32 * h) * 16 + i;
+}
+
 __global__ __launch_bounds__(256) void k_stage(StageArgs a) {
   __shared__ float tv[32][33];
   __shared__ float tm[32][33];
@@ -46,18 +53,25 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a) {
       }
       acc += (double)m * (double)v * (double)v;
     }
-    a.D[(int64_t)r * a.p_pad + c] = v;
-    a.Mw[(int64_t)r * a.p_pad + c] = m;
     tv[ty + 8 * q][tx] = v;
     tm[ty + 8 * q][tx] = m;
   }
   __syncthreads();
-  if (a.DT) {
+  // Tiled copies: slot o of a tile holds (row, col) = (acc_row(o % 16, o / 512), (o / 16) % 32).
+  const int64_t tileA = ((int64_t)blockIdx.x * (a.n_pad / 32) + blockIdx.y) * 1024;
+  const int64_t tileB = ((int64_t)blockIdx.y * (a.p_pad / 32) + blockIdx.x) * 1024;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = cb + ty + 8 * q, r = rb + tx;
-      a.DT[(int64_t)c * a.n_pad + r] = tv[tx][ty + 8 * q];
-      a.MwT[(int64_t)c * a.n_pad + r] = tm[tx][ty + 8 * q];
+  for (int q = 0; q < 4; ++q) {
+    const int o = threadIdx.x + 256 * q;
+    const int ln = o >> 4, i = o & 15;
+    const int tr = acc_row(i, ln >> 5), tcol = ln & 31;
+    if (a.D) {
+      a.D[tileA + o] = tv[tr][tcol];
+      a.Mw[tileA + o] = tm[tr][tcol];
+    }
+    if (a.DT) {
+      a.DT[tileB + o] = tv[tcol][tr];
+      a.MwT[tileB + o] = tm[tcol][tr];
     }
   }
   red[threadIdx.x] = acc;
@@ -176,37 +190,75 @@ hipError_t launch_factor_out(const float* t, int rows, int rows_pad, int K, int 
 }
 
 // ---------------------------------------------------------------------------
-// W-rule finish: fixed-order sum over the split partials, then the update
+// Finish of a split half-step: fixed-order sum over the partials, the update,
+// every layout; block (0, 0) also sums the H-rule objective partials.
+// Block = 64 columns x 4 groups of splits.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_row_update(RowUpdateArgs a) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_finish(FinishArgs a) {
+  __shared__ double rn[4][64];
+  __shared__ double rd[4][64];
+  __shared__ double rj[256];
+  const int cx = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cx;
   const int k = blockIdx.y;
-  if (c >= a.C_pad) return;
-  const int64_t stride = (int64_t)a.KP * a.C_pad;
-  const float* pn = a.partial + (int64_t)k * a.C_pad + c;
   double num = 0.0, den = 0.0;
-  for (int s = 0; s < a.S; ++s) {
-    num += pn[(int64_t)(2 * s) * stride];
-    den += pn[(int64_t)(2 * s + 1) * stride];
+  if (c < a.C_pad) {
+    const int64_t stride = (int64_t)a.KP * a.C_pad;
+    const float* pn = a.partial + (int64_t)k * a.C_pad + c;
+    for (int s = g; s < a.S; s += 4) {
+      num += pn[(int64_t)(2 * s) * stride];
+      den += pn[(int64_t)(2 * s + 1) * stride];
+    }
   }
-  float nv = 0.f;
-  if (k < a.K && c < a.C_valid) nv = mu_apply(a.m[(int64_t)c * a.KP + k], (float)num, (float)den, a.eps);
-  a.m[(int64_t)c * a.KP + k] = nv;
-  a.t[(int64_t)k * a.C_pad + c] = nv;
-  if (a.prec == PREC_FP32) {
-    a.tp[(int64_t)k * a.C_pad + perm_f32(c)] = nv;
-  } else {
-    __bf16 hi, lo;
-    split_bf16(nv, hi, lo);
-    a.mh[(int64_t)c * a.KP + k] = hi;
-    a.ml[(int64_t)c * a.KP + k] = lo;
-    a.tph[(int64_t)k * a.C_pad + perm_bf16(c)] = hi;
-    a.tpl[(int64_t)k * a.C_pad + perm_bf16(c)] = lo;
+  rn[g][cx] = num;
+  rd[g][cx] = den;
+  __syncthreads();
+  if (g == 0 && c < a.C_pad) {
+    num = ((rn[0][cx] + rn[1][cx]) + rn[2][cx]) + rn[3][cx];
+    den = ((rd[0][cx] + rd[1][cx]) + rd[2][cx]) + rd[3][cx];
+    float nv = 0.f;
+    const int64_t it = (int64_t)k * a.C_pad + c;
+    if (k < a.K && c < a.C_valid) nv = mu_apply_d(a.t[it], num, den, a.eps);
+    a.t[it] = nv;
+    a.m[(int64_t)c * a.KP + k] = nv;
+    if (a.prec == PREC_FP32) {
+      a.tp[(int64_t)k * a.C_pad + perm_f32(c)] = nv;
+    } else {
+      __bf16 hi, lo;
+      split_bf16(nv, hi, lo);
+      a.mh[(int64_t)c * a.KP + k] = hi;
+      a.ml[(int64_t)c * a.KP + k] = lo;
+      a.tph[(int64_t)k * a.C_pad + perm_bf16(c)] = hi;
+      a.tpl[(int64_t)k * a.C_pad + perm_bf16(c)] = lo;
+    }
+  }
+  if (a.Jpart && blockIdx.x == 0 && blockIdx.y == 0) {
+    double sj = 0.0;
+    for (int i = threadIdx.x; i < a.nJ; i += 256) sj += a.Jpart[i];
+    rj[threadIdx.x] = sj;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) rj[threadIdx.x] += rj[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const int t = *a.iter;
+      a.Jhist[t] = rj[0];
+      *a.iter = t + 1;
+      if (!isfinite(rj[0])) atomicOr(a.status, 8);
+    }
   }
 }
 
-hipError_t launch_row_update(const RowUpdateArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_row_update, dim3((a.C_pad + 255) / 256, a.KP), dim3(256), 0, s, a);
+hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3((a.C_pad + 63) / 64, a.KP), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
+
+hipError_t launch_set_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);
   return hipGetLastError();
 }
 

@@ -1,45 +1,60 @@
 // Fused multiplicative-update half-step (Eq. 3 of arXiv:2309.04623) for
 // gfx950.
 //
-// One workgroup is one wave and owns a 32-column tile of the data matrix D
-// (R x C) over a range of rows.  For every block of 32 rows it
+// A workgroup of NW waves owns one 32-column tile of the data matrix D
+// (R x C) and a chunk of its 32-row tiles; wave w takes row tiles w, w+NW, ...
+// For every 32x32 tile a wave
 //   1. forms Y = L[rows] * Rt[:, cols] on MFMA (the model W H, Eq. 1),
-//   2. reads D and the weights Mw for the same 32x32 tile and forms
-//      A = Mw o D, Z = Mw o Y and the residual term Mw (D - Y)^2 (Eq. 2),
-//   3. accumulates num += L^T A and den += L^T Z on MFMA, with Y, A and Z fed
-//      from the accumulator registers of step 1 without any re-layout: the
-//      32x32 accumulator layout is the B-operand layout of the next 32x32
-//      MFMA up to a fixed permutation of the reduction index, and the L^T
-//      operand is stored with that permutation applied.
-// Y, A and Z never leave registers.
+//   2. reads D and the weights Mw for the same tile, stored in MFMA
+//      accumulator order so that each lane fetches its 16 values with four
+//      16-byte loads (the next tile is prefetched while this one computes),
+//      and forms A = Mw o D, Z = Mw o Y and the residual term Mw (D - Y)^2
+//      (Eq. 2),
+//   3. accumulates num += L^T A and den += L^T Z on MFMA, fed straight from
+//      the registers of step 1: the 32x32 accumulator layout is the
+//      B-operand layout of the next 32x32 MFMA up to a fixed permutation of
+//      the reduction index, and the L^T operand is stored with that
+//      permutation applied.
+// Y, A and Z never leave registers.  The NW partial sums are combined
+// through LDS in a fixed order (bitwise reproducible).
 //
 // Modes:
-//   MODE_UPDATE  the block covers all rows: apply Rt <- max(Rt o num/den, eps)
-//                to its tile and write the layouts the other half-step reads
-//                (H-rule of Eq. 3 on V; also yields J for the current W, H).
-//   MODE_SPLIT   the block covers one chunk of rows: write num/den partials,
-//                finished by the row-update kernel (W-rule, on V^T).
+//   MODE_UPDATE  one chunk covers all rows: apply Rt <- max(Rt o num/den, eps)
+//                to the tile and write the layouts the other half-step reads
+//                (the H-rule of Eq. 3 on V; also yields J for W, H).
+//   MODE_SPLIT   write num/den partials for the chunk; the finish kernel sums
+//                them (the W-rule, on V^T).
 //   MODE_OBJ     objective only.
 //
 // FP32 products use v_mfma_f32_32x32x2_f32.  The split-precision products
-// use v_mfma_f32_32x32x16_bf16 three times per product (hi*hi + hi*lo +
-// lo*hi), FP32 accumulation.
+// use v_mfma_f32_32x32x16_bf16 three times (hi*hi + hi*lo + lo*hi) with FP32
+// accumulation.
 
 #include "device_common.hpp"
 #include "kernels.hpp"
 
 namespace nmf {
 
-template <int PREC, int KP, int MODE>
-__global__ __launch_bounds__(64) void k_dual(DualArgs a) {
+__device__ __forceinline__ void load_tile(const float* p, f32x4 (&v)[4]) {
+  const f32x4* q = reinterpret_cast<const f32x4*>(p);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(q + u);
+}
+
+template <int PREC, int KP, int MODE, int NW>
+__global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
   static_assert(KP % 32 == 0, "KP must be a multiple of 32");
   constexpr int MT = KP / 32;  // 32-row tiles of the num/den outputs
-  const int lane = threadIdx.x;
+  __shared__ float red[(NW > 1) ? (NW - 1) * 2 * 16 * 64 : 1];
+  __shared__ double jred[NW];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int col = lane & 31;
   const int half = lane >> 5;
-  const int c0 = blockIdx.x * TILE;
-  const int r_begin = blockIdx.y * a.rows_per_split;
-  const int r_end = min(r_begin + a.rows_per_split, a.R_pad);
+  const int tc = blockIdx.x;
+  const int c0 = tc * TILE;
+  const int t_begin = blockIdx.y * a.tiles_per_split;
+  const int t_end = min(t_begin + a.tiles_per_split, a.RT);
 
   // ---- right-factor tile, resident for the whole block ------------------
   // FP32: product step j uses reduction index half*KP/2 + j.
@@ -74,19 +89,24 @@ __global__ __launch_bounds__(64) void k_dual(DualArgs a) {
   }
   double jacc = 0.0;
 
-  for (int r0 = r_begin; r0 < r_end; r0 += TILE) {
-    // ---- data tile in accumulator layout --------------------------------
-    float dv[16], mv[16];
-    {
-      const float* dp = a.D + (int64_t)(r0 + 4 * half) * a.ldd + c0 + col;
-      const float* mp = a.Mw + (int64_t)(r0 + 4 * half) * a.ldd + c0 + col;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int64_t off = (int64_t)(8 * (i >> 2) + (i & 3)) * a.ldd;
-        dv[i] = __builtin_nontemporal_load(dp + off);
-        mv[i] = __builtin_nontemporal_load(mp + off);
-      }
+  const int64_t tile_base = (int64_t)tc * a.RT;
+  const float* dcol = a.D + tile_base * 1024 + lane * 16;
+  const float* mcol = a.Mw + tile_base * 1024 + lane * 16;
+  int tr = t_begin + wave;
+  f32x4 dv[4], mv[4];
+  if (tr < t_end) {
+    load_tile(dcol + (int64_t)tr * 1024, dv);
+    load_tile(mcol + (int64_t)tr * 1024, mv);
+  }
+  for (; tr < t_end; tr += NW) {
+    // prefetch the next tile of this wave
+    f32x4 dn[4], mn[4];
+    const int trn = tr + NW;
+    if (trn < t_end) {
+      load_tile(dcol + (int64_t)trn * 1024, dn);
+      load_tile(mcol + (int64_t)trn * 1024, mn);
     }
+    const int r0 = tr * TILE;
 
     // ---- Y = L[r0:r0+32, :] * Rt -----------------------------------------
     f32x16 y = zero16();
@@ -116,11 +136,13 @@ __global__ __launch_bounds__(64) void k_dual(DualArgs a) {
     float js = 0.f;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      av[i] = mv[i] * dv[i];
-      zv[i] = mv[i] * y[i];
+      const float d = dv[i >> 2][i & 3];
+      const float m = mv[i >> 2][i & 3];
+      av[i] = m * d;
+      zv[i] = m * y[i];
       if constexpr (MODE != MODE_SPLIT) {
-        const float d = dv[i] - y[i];
-        js = fmaf(mv[i] * d, d, js);
+        const float r = d - y[i];
+        js = fmaf(m * r, r, js);
       }
     }
     if constexpr (MODE != MODE_SPLIT) jacc += (double)js;
@@ -168,15 +190,52 @@ __global__ __launch_bounds__(64) void k_dual(DualArgs a) {
         }
       }
     }
-  }
-
-  // ---- objective partial (fixed-order wave sum) ---------------------------
-  if constexpr (MODE != MODE_SPLIT) {
-    if (a.Jpart) {
-      const double js = wave_sum(jacc);
-      if (lane == 0) a.Jpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = js;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      dv[u] = dn[u];
+      mv[u] = mn[u];
     }
   }
+
+  // ---- combine the NW waves' sums in a fixed order -----------------------
+  if constexpr (NW > 1 && MODE != MODE_OBJ) {
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      if (wave > 0) {
+        float* dst = red + (wave - 1) * 2 * 1024;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          dst[i * 64 + lane] = num[t][i];
+          dst[1024 + i * 64 + lane] = den[t][i];
+        }
+      }
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int w = 0; w < NW - 1; ++w) {
+          const float* src = red + w * 2 * 1024;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            num[t][i] += src[i * 64 + lane];
+            den[t][i] += src[1024 + i * 64 + lane];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if constexpr (MODE != MODE_SPLIT) {
+    const double js = wave_sum(jacc);
+    if (lane == 0) jred[wave] = js;
+    __syncthreads();
+    if (threadIdx.x == 0 && a.Jpart) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s += jred[w];
+      a.Jpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+  }
+  if (wave != 0) return;
 
   if constexpr (MODE == MODE_SPLIT) {
     float* pn = a.partial + (int64_t)blockIdx.y * 2 * KP * a.C_pad;
@@ -219,38 +278,42 @@ __global__ __launch_bounds__(64) void k_dual(DualArgs a) {
   }
 }
 
-template <int PREC, int KP>
-static hipError_t launch_kp(int mode, const DualArgs& a, dim3 g, hipStream_t s) {
-  switch (mode) {
-    case MODE_UPDATE:
-      hipLaunchKernelGGL((k_dual<PREC, KP, MODE_UPDATE>), g, dim3(64), 0, s, a);
-      break;
-    case MODE_SPLIT:
-      hipLaunchKernelGGL((k_dual<PREC, KP, MODE_SPLIT>), g, dim3(64), 0, s, a);
-      break;
-    default:
-      hipLaunchKernelGGL((k_dual<PREC, KP, MODE_OBJ>), g, dim3(64), 0, s, a);
-      break;
+template <int PREC, int KP, int MODE>
+static hipError_t launch_mode(int nw, const DualArgs& a, dim3 g, hipStream_t s) {
+  switch (nw) {
+    case 1: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 1>), g, dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 2>), g, dim3(128), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 4>), g, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+template <int PREC, int KP>
+static hipError_t launch_kp(int mode, int nw, const DualArgs& a, dim3 g, hipStream_t s) {
+  switch (mode) {
+    case MODE_UPDATE: return launch_mode<PREC, KP, MODE_UPDATE>(nw, a, g, s);
+    case MODE_SPLIT: return launch_mode<PREC, KP, MODE_SPLIT>(nw, a, g, s);
+    default: return launch_mode<PREC, KP, MODE_OBJ>(nw, a, g, s);
+  }
+}
+
 template <int PREC>
-static hipError_t launch_prec(int kp, int mode, const DualArgs& a, dim3 g, hipStream_t s) {
+static hipError_t launch_prec(int kp, int mode, int nw, const DualArgs& a, dim3 g, hipStream_t s) {
   switch (kp) {
-    case 32: return launch_kp<PREC, 32>(mode, a, g, s);
-    case 64: return launch_kp<PREC, 64>(mode, a, g, s);
-    case 96: return launch_kp<PREC, 96>(mode, a, g, s);
-    case 128: return launch_kp<PREC, 128>(mode, a, g, s);
+    case 32: return launch_kp<PREC, 32>(mode, nw, a, g, s);
+    case 64: return launch_kp<PREC, 64>(mode, nw, a, g, s);
+    case 96: return launch_kp<PREC, 96>(mode, nw, a, g, s);
+    case 128: return launch_kp<PREC, 128>(mode, nw, a, g, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_dual(int prec, int kp, int mode, const DualArgs& a, int grid_x, int grid_y,
-                       hipStream_t s) {
+hipError_t launch_dual(int prec, int kp, int mode, int nw, const DualArgs& a, int grid_x,
+                       int grid_y, hipStream_t s) {
   const dim3 g(grid_x, grid_y);
-  if (prec == PREC_FP32) return launch_prec<PREC_FP32>(kp, mode, a, g, s);
-  return launch_prec<PREC_BF16X3>(kp, mode, a, g, s);
+  if (prec == PREC_FP32) return launch_prec<PREC_FP32>(kp, mode, nw, a, g, s);
+  return launch_prec<PREC_BF16X3>(kp, mode, nw, a, g, s);
 }
 
 }  // namespace nmf

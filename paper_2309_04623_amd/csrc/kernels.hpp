@@ -7,18 +7,24 @@
 
 namespace nmf {
 
-// One multiplicative-update half-step over a data matrix D (R x C, stored
-// padded to R_pad x C_pad, row-major) with weights Mw of the same shape:
+// One multiplicative-update half-step over a data matrix D (R x C, padded to
+// multiples of 32) with weights Mw of the same shape:
 //   Y   = L Rt                      (L: R x K rows, Rt: K x C tile)
 //   num = L^T (Mw o D),  den = L^T (Mw o Y)   (reduced over R)
 // and optionally J = sum Mw (D - Y)^2.
 // The H-rule of Eq. 3 is this step on (D = V, L = W, Rt = H); the W-rule is
 // the same step on the transposed problem (D = V^T, L = H^T, Rt = W^T).
+//
+// D and Mw are stored tiled: 32x32 tiles, column-tile-major (tile (tr, tc)
+// at index tc * RT + tr), and inside a tile in MFMA accumulator order: the
+// 16 values of lane l (column l % 32, rows acc_row(i, l / 32)) at
+// l * 16 + i.
 struct DualArgs {
   const float* D;
   const float* Mw;
-  int64_t ldd;
-  int R_pad, C_pad, C_valid, rows_per_split;
+  int RT;               // row tiles (R_pad / 32)
+  int tiles_per_split;  // row tiles per grid-y chunk
+  int C_pad, C_valid;
   // left factor rows (R_pad x KP): FP32, or the bf16 hi/lo split
   const float* L;
   const __bf16* Lh;
@@ -48,25 +54,35 @@ struct DualArgs {
 
 enum DualMode { MODE_UPDATE = 0, MODE_SPLIT = 1, MODE_OBJ = 2 };
 
-hipError_t launch_dual(int prec, int kp, int mode, const DualArgs& a, int grid_x, int grid_y,
-                       hipStream_t s);
+// nw = waves per workgroup (1, 2 or 4); grid = (C_pad / 32, splits).
+hipError_t launch_dual(int prec, int kp, int mode, int nw, const DualArgs& a, int grid_x,
+                       int grid_y, hipStream_t s);
 
-// Finishes the W-rule: sums split partials (fixed order), applies the update
-// to the factor rows and refreshes every layout of the factor.
-struct RowUpdateArgs {
+// Finishes a split half-step: sums the partials in a fixed order, applies
+// the update to the factor (old value read from t, the KP x C_pad layout)
+// and refreshes every layout.  Optionally also sums the objective partials
+// of the preceding H-rule pass into Jhist[*iter] and advances *iter.
+struct FinishArgs {
   const float* partial;  // [S][2][KP][C_pad]
   int S, KP, C_pad, C_valid, K;
   float eps;
-  float* m;          // C_pad x KP master FP32 (updated in place)
+  int prec;
+  float* m;          // C_pad x KP
   __bf16* mh;        // C_pad x KP bf16 hi/lo
   __bf16* ml;
-  float* t;          // KP x C_pad transposed FP32
-  float* tp;         // KP x C_pad transposed, FP32 operand order
-  __bf16* tph;       // KP x C_pad transposed, bf16 operand order
+  float* t;          // KP x C_pad (holds the current values)
+  float* tp;         // KP x C_pad permuted, FP32 operand order
+  __bf16* tph;       // KP x C_pad permuted, bf16 operand order
   __bf16* tpl;
-  int prec;
+  const double* Jpart;  // nullable
+  int nJ;
+  double* Jhist;
+  int* iter;
+  int* status;
 };
-hipError_t launch_row_update(const RowUpdateArgs& a, hipStream_t s);
+hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
+
+hipError_t launch_set_int(int* p, int v, hipStream_t s);
 
 // Layout fill of a factor: from a user matrix (rows x K, row-major, or
 // K x rows if ``user_is_kxr``), or from the seeded generator when src is
@@ -92,19 +108,20 @@ hipError_t launch_factor_fill(const FactorFillArgs& a, hipStream_t s);
 hipError_t launch_factor_out(const float* t, int rows, int rows_pad, int K, int KP,
                              int out_is_kxr, float* out, hipStream_t s);
 
-// Data staging: Vhat = V where M > 0 else 0 into padded D and its transpose,
-// weights likewise; flags bad data under positive weight; per-block partial
-// sums of M * Vhat^2.
+// Data staging: Vhat = V where M > 0 else 0 and the weights, written as the
+// tiled layouts of the two half-steps (D: n x p tiles, DT: p x n tiles);
+// flags bad data under positive weight; per-block partial sums of
+// M * Vhat^2.
 struct StageArgs {
   const float* V;
   const float* M;
   int64_t n, p;
   int n_pad, p_pad;
   int clip_negative;
-  float* D;    // n_pad x p_pad
-  float* Mw;   // n_pad x p_pad
-  float* DT;   // p_pad x n_pad (nullable)
-  float* MwT;  // p_pad x n_pad (nullable)
+  float* D;    // tiled n_pad x p_pad (nullable)
+  float* Mw;
+  float* DT;   // tiled p_pad x n_pad (nullable)
+  float* MwT;
   int* status; // bit 0: non-finite data, bit 1: negative data, bit 2: bad weight
   double* part;
 };
