@@ -171,14 +171,26 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
                 const float* M_T, int64_t f, const nmf_params* prm, const float* C_init,
                 float* C_out, double* obj_out, nmf_report* rep, void* stream);
 
-/* Same iteration for frames stored as CSR rows: frame i owns entries
- * offsets[i] .. offsets[i+1]-1 of pix (int32 pixel index in [0, p)),
- * val (float32 data) and wt (float32 weight; NULL = all ones).  Pixel
- * indices within a frame must be distinct.  offsets: f + 1 int64, device. */
+/* Same iteration for frames stored as CSR rows, always through the masked
+ * Gram form: frame i owns entries offsets[i] .. offsets[i+1]-1 of pix (int32
+ * pixel index in [0, p)), val (float32 data) and wt (float32 weight; NULL =
+ * all ones); pixels absent from a frame carry weight 0.  Pixel indices
+ * within a frame must be distinct.  offsets: f + 1 int64 (device) with
+ * 0 <= offsets[i] <= offsets[i+1] <= nnz; entries that break this, or a
+ * pixel index outside [0, p), are skipped and reported as NMF_ERR_ARG.
+ * All frames run in one persistent launch that takes frames from a device
+ * work queue, longest first.
+ *   frame_ticks : nullable, 2 * f uint64 (device): device clock at which
+ *                 each frame was taken from the queue and finished (see
+ *                 nmf_device_clock_khz).                                  */
 int nmf_project_ragged(nmf_handle h, const float* H, int64_t k, int64_t p, int64_t f,
-                       const int64_t* offsets, const int32_t* pix, const float* val,
-                       const float* wt, const nmf_params* prm, const float* C_init,
-                       float* C_out, double* obj_out, nmf_report* rep, void* stream);
+                       const int64_t* offsets, int64_t nnz, const int32_t* pix,
+                       const float* val, const float* wt, const nmf_params* prm,
+                       const float* C_init, float* C_out, uint64_t* frame_ticks,
+                       nmf_report* rep, void* stream);
+
+/* Frequency (kHz) of the device clock used by frame_ticks. */
+double nmf_device_clock_khz(nmf_handle h);
 
 /* ---- subtraction -----------------------------------------------------------
  * Sec. 1 and Sec. 4.1: the model PSF c_f H is removed from each frame:

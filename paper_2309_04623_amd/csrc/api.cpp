@@ -50,6 +50,9 @@ struct nmf_handle_s {
   std::vector<Rec> pending;
   double prof_ms[NMF_K_COUNT] = {};
   int64_t prof_n[NMF_K_COUNT] = {};
+  // captured launch sequences, keyed by operation and every argument
+  hipStream_t cap = nullptr;
+  std::unordered_map<std::string, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -163,6 +166,47 @@ hipError_t prof_drain(nmf_handle h) {
   }
   h->pending.clear();
   return hipSuccess;
+}
+
+// Runs ``enqueue(stream)`` either directly on ``s`` (timing on, or graphs
+// off) or as a hipGraph captured once on the handle's capture stream and
+// replayed on ``s``; the graph is cached under ``key``.
+template <typename F>
+hipError_t run_graph(nmf_handle h, const std::string& key, hipStream_t s, F enqueue) {
+  if (h->prof) return enqueue(s);
+  auto it = h->graphs.find(key);
+  if (it == h->graphs.end()) {
+    hipError_t e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t ee = enqueue(h->cap);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(h->cap, &graph);
+    if (ee != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return ee;
+    }
+    if (e != hipSuccess) return e;
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    if (h->graphs.size() > 64) {
+      for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+      h->graphs.clear();
+    }
+    it = h->graphs.emplace(key, exec).first;
+  }
+  return hipGraphLaunch(it->second, s);
+}
+
+std::string key_of(const char* op, std::initializer_list<uint64_t> vals) {
+  std::string k(op);
+  char buf[24];
+  for (uint64_t v : vals) {
+    std::snprintf(buf, sizeof(buf), ":%llx", (unsigned long long)v);
+    k += buf;
+  }
+  return k;
 }
 
 inline int round_up(int64_t x, int m) { return (int)((x + m - 1) / m * m); }
@@ -321,9 +365,10 @@ int nmf_create(int hip_device, nmf_handle* out) {
     delete h;
     return fail(NMF_ERR_HIP, "hipSetDevice failed");
   }
-  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+      hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
     delete h;
-    return fail(NMF_ERR_HIP, "hipEventCreate failed");
+    return fail(NMF_ERR_HIP, "hipEventCreate/hipStreamCreate failed");
   }
   *out = h;
   return NMF_OK;
@@ -338,6 +383,8 @@ int nmf_destroy(nmf_handle h) {
   if (h->pinned) (void)hipHostFree(h->pinned);
   (void)prof_drain(h);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   delete h;
@@ -382,7 +429,7 @@ constexpr int SIMDS = 1024;  // 256 compute units x 4
 PassCfg cfg_whole(int col_tiles, int RT, int KP, int req_nw) {
   PassCfg c;
   const int cap = SIMDS * occupancy_for(KP);
-  c.nw = 1;
+  c.nw = KP >= 128 ? 2 : 1;  // one wave per workgroup spills at KP = 128
   if (req_nw > 0) {
     c.nw = req_nw;
   } else {
@@ -451,6 +498,108 @@ FinishArgs finish_args(const float* partial, int S, const Factor& f, int C_valid
   a.tph = f.tph;
   a.tpl = f.tpl;
   return a;
+}
+
+constexpr int GRAM_K_MAX = 200;  // G (K x K FP32) must fit the 160 KB LDS
+
+struct GramCall {
+  const float* H = nullptr;
+  int K = 0;
+  int64_t p = 0, f = 0;
+  const float* T = nullptr;   // dense frames
+  const float* MT = nullptr;
+  const int64_t* offsets = nullptr;  // CSR frames
+  int64_t nnz = 0;
+  const int32_t* pix = nullptr;
+  const float* val = nullptr;
+  const float* wt = nullptr;
+  const nmf_params* prm = nullptr;
+  const float* C_init = nullptr;
+  float* C_out = nullptr;
+  uint64_t* ticks = nullptr;
+};
+
+// Masked-Gram projection of dense or CSR frames: H layouts, (for CSR) the
+// longest-first order, and the persistent kernel, captured as one graph.
+int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep) {
+  const bool ragged = c.offsets != nullptr;
+  const int K = c.K, KP = kp_for(K);
+  const int p_pad = round_up(c.p, 32);
+  DeviceGuard g(h->device);
+  if (!g.ok) return fail(NMF_ERR_HIP, "hipSetDevice failed");
+  int rc;
+  Factor Hf;
+  int *queue, *stat, *order = nullptr;
+  if ((rc = factor_alloc(h, "GH", (int)c.p, p_pad, KP, &Hf)) || (rc = ws(h, "gqueue", 1, &queue)) ||
+      (rc = ws(h, "gstat", 1, &stat)))
+    return rc;
+  const bool sorted = ragged && c.f <= MAX_SORT_FRAMES && c.f > 1;
+  if (sorted && (rc = ws(h, "gorder", (size_t)c.f, &order))) return rc;
+  GramArgs a{};
+  a.HT = Hf.m;
+  a.K = K;
+  a.P = (int)c.p;
+  a.F = (int)c.f;
+  a.T = c.T;
+  a.MT = c.MT;
+  a.offsets = c.offsets;
+  a.nnz = c.nnz;
+  a.pix = c.pix;
+  a.val = c.val;
+  a.wt = c.wt;
+  a.order = order;
+  a.C_init = c.C_init;
+  a.seed = c.prm->seed;
+  a.iters = c.prm->max_iter;
+  a.eps = c.prm->floor_eps;
+  a.clip_negative = (c.prm->flags & NMF_F_CLIP_NEGATIVE) ? 1 : 0;
+  a.C_out = c.C_out;
+  a.queue = queue;
+  a.status = stat;
+  a.ticks = c.ticks;
+  const FactorFillArgs fa = fill_args(Hf, c.H, 1, 0, 1, K);
+  auto enqueue = [&](hipStream_t s) -> hipError_t {
+    hipError_t e;
+    if ((e = timed(h, NMF_K_OTHER, s, [&]() { return launch_set_int(queue, 0, s); }))) return e;
+    if ((e = timed(h, NMF_K_OTHER, s, [&]() { return launch_set_int(stat, 0, s); }))) return e;
+    if ((e = timed(h, NMF_K_OTHER, s, [&]() { return launch_factor_fill(fa, s); }))) return e;
+    if (sorted &&
+        (e = timed(h, NMF_K_OTHER, s, [&]() { return launch_frame_order(c.offsets, a.F, order, s); })))
+      return e;
+    return timed(h, NMF_K_PROJECT, s, [&]() { return launch_gram(KP, ragged, a, 0, s, nullptr); });
+  };
+  const std::string key =
+      key_of(ragged ? "gramR" : "gramD",
+             {(uint64_t)c.H, (uint64_t)K, (uint64_t)c.p, (uint64_t)c.f, (uint64_t)c.T,
+              (uint64_t)c.MT, (uint64_t)c.offsets, (uint64_t)c.nnz, (uint64_t)c.pix,
+              (uint64_t)c.val, (uint64_t)c.wt, (uint64_t)c.C_init, (uint64_t)c.C_out,
+              (uint64_t)c.ticks, (uint64_t)c.prm->seed, (uint64_t)c.prm->max_iter,
+              (uint64_t)c.prm->flags, (uint64_t)__builtin_bit_cast(uint32_t, c.prm->floor_eps),
+              (uint64_t)Hf.m, (uint64_t)queue, (uint64_t)stat, (uint64_t)order});
+  HIP_TRY(hipEventRecord(h->ev0, s));
+  HIP_TRY(run_graph(h, key, s, enqueue));
+  HIP_TRY(hipEventRecord(h->ev1, s));
+  if (c.prm->flags & NMF_F_ASYNC) return NMF_OK;
+  int st = 0;
+  HIP_TRY(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(prof_drain(h));
+  if (st & 16) return fail(NMF_ERR_ARG, "CSR offsets or pixel indices out of range");
+  if (c.prm->flags & NMF_F_VALIDATE_DATA) {
+    if ((rc = status_from_stage(st))) return rc;
+  } else if ((rc = status_from_stage(st & 4))) {
+    return rc;
+  }
+  if (rep) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
+    rep->iters_run = c.prm->max_iter;
+    rep->status_flags = 0;
+    rep->objective = 0.0;
+    rep->objective_rel = 0.0;
+    rep->elapsed_ms = ms;
+  }
+  return NMF_OK;
 }
 
 }  // namespace
@@ -692,9 +841,29 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
     return fail(NMF_ERR_ARG, "forbidden aliasing between arguments");
   const int K = (int)k;
   const int KP = kp_for(K);
+  if (prm->flags & NMF_F_MASKED_GRAM) {
+    if (K > GRAM_K_MAX) return fail(NMF_ERR_UNSUPPORTED, "masked-Gram projection needs k <= 200");
+    if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+    GramCall gc{};
+    gc.H = H;
+    gc.K = K;
+    gc.p = p;
+    gc.f = f;
+    gc.T = T;
+    gc.MT = M_T;
+    gc.prm = prm;
+    gc.C_init = C_init;
+    gc.C_out = C_out;
+    int rc2 = project_gram(h, gc, (hipStream_t)stream, rep);
+    if (rc2 < 0 || !obj_out) return rc2;
+    DeviceGuard g(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    LAUNCH(NMF_K_OTHER, launch_frame_objective(H, C_out, T, M_T, f, K, p, obj_out, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(prof_drain(h));
+    return rc2;
+  }
   if (KP > KP_MAX) return fail(NMF_ERR_UNSUPPORTED, "k > 128 is not supported by this build");
-  if (prm->flags & NMF_F_MASKED_GRAM)
-    return fail(NMF_ERR_UNSUPPORTED, "masked-Gram projection is not available in this build");
   if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
   const int prec = prm->precision;
   DeviceGuard g(h->device);
@@ -761,13 +930,50 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
 }
 
 int nmf_project_ragged(nmf_handle h, const float* H, int64_t k, int64_t p, int64_t f,
-                       const int64_t* offsets, const int32_t* pix, const float* val,
-                       const float* wt, const nmf_params* prm, const float* C_init,
-                       float* C_out, double* obj_out, nmf_report* rep, void* stream) {
-  (void)H; (void)k; (void)p; (void)f; (void)offsets; (void)pix; (void)val; (void)wt;
-  (void)prm; (void)C_init; (void)C_out; (void)obj_out; (void)rep; (void)stream;
+                       const int64_t* offsets, int64_t nnz, const int32_t* pix,
+                       const float* val, const float* wt, const nmf_params* prm,
+                       const float* C_init, float* C_out, uint64_t* frame_ticks,
+                       nmf_report* rep, void* stream) {
+  if (!H || !offsets || !C_out || (nnz > 0 && (!pix || !val)))
+    return fail(NMF_ERR_ARG, "NULL array argument");
+  int rc = check_dims(f, p, "project_ragged");
+  if (rc) return rc;
+  if (f > 0x7fffffff || p > 0x7fffffff) return fail(NMF_ERR_SHAPE, "f and p must fit in int32");
+  if (nnz < 0) return fail(NMF_ERR_SHAPE, "nnz must be >= 0");
+  if ((rc = check_params(prm, f, p, false))) return rc;
+  if (prm->k != k) return fail(NMF_ERR_ARG, "params.k must equal k");
+  if (k > p) return fail(NMF_ERR_ARG, "k must not exceed p");
+  if (k > GRAM_K_MAX) return fail(NMF_ERR_UNSUPPORTED, "ragged projection needs k <= 200");
+  if (prm->precision != NMF_PREC_FP32)
+    return fail(NMF_ERR_UNSUPPORTED, "ragged projection runs FP32 products in this build");
+  if (rep && rep->struct_size != sizeof(nmf_report))
+    return fail(NMF_ERR_ARG, "nmf_report.struct_size mismatch");
+  if ((const float*)C_out == H || (const float*)C_out == val || (const float*)C_out == wt)
+    return fail(NMF_ERR_ARG, "forbidden aliasing between arguments");
   if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
-  return fail(NMF_ERR_UNSUPPORTED, "ragged projection is not available in this build");
+  GramCall gc{};
+  gc.H = H;
+  gc.K = (int)k;
+  gc.p = p;
+  gc.f = f;
+  gc.offsets = offsets;
+  gc.nnz = nnz;
+  gc.pix = pix;
+  gc.val = val;
+  gc.wt = wt;
+  gc.prm = prm;
+  gc.C_init = C_init;
+  gc.C_out = C_out;
+  gc.ticks = frame_ticks;
+  return project_gram(h, gc, (hipStream_t)stream, rep);
+}
+
+double nmf_device_clock_khz(nmf_handle h) {
+  if (!h) return 0.0;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) != hipSuccess)
+    return 0.0;
+  return (double)khz;
 }
 
 // ---------------------------------------------------------------------------

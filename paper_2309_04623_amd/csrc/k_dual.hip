@@ -92,46 +92,99 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
   const int64_t tile_base = (int64_t)tc * a.RT;
   const float* dcol = a.D + tile_base * 1024 + lane * 16;
   const float* mcol = a.Mw + tile_base * 1024 + lane * 16;
-  int tr = t_begin + wave;
-  f32x4 dv[4], mv[4];
-  if (tr < t_end) {
-    load_tile(dcol + (int64_t)tr * 1024, dv);
-    load_tile(mcol + (int64_t)tr * 1024, mv);
-  }
-  for (; tr < t_end; tr += NW) {
-    // prefetch the next tile of this wave
-    f32x4 dn[4], mn[4];
-    const int trn = tr + NW;
-    if (trn < t_end) {
-      load_tile(dcol + (int64_t)trn * 1024, dn);
-      load_tile(mcol + (int64_t)trn * 1024, mn);
-    }
-    const int r0 = tr * TILE;
+  // Operand registers of the current tile: the L rows (GEMM1 A operand) and
+  // the permuted L^T block (GEMM2 A operand).
+  constexpr bool PRELOAD = KP <= 64;
+  constexpr int NL_F32 = (PREC == PREC_FP32) ? KP / 8 : 1;
+  constexpr int NL_BF = (PREC == PREC_FP32) ? 1 : KP / 16;
+  constexpr int NT_F32 = (PREC == PREC_FP32) ? MT * 4 : 1;
+  constexpr int NT_BF = (PREC == PREC_FP32) ? 1 : MT * 2;
+  f32x4 lq[NL_F32];
+  bf16x8 lh[NL_BF], ll[NL_BF];
+  f32x4 tq[NT_F32];
+  bf16x8 th[NT_BF], tl[NT_BF];
 
-    // ---- Y = L[r0:r0+32, :] * Rt -----------------------------------------
+  // One tile: consume (dv, mv), prefetch the wave's next tile into (dn, mn).
+  auto step = [&](const int tr, const f32x4 (&dv)[4], const f32x4 (&mv)[4], f32x4 (&dn)[4],
+                  f32x4 (&mn)[4]) {
+    const int r0 = tr * TILE;
+    // ---- 1. all operand loads of this tile (L2-resident factors) ----------
+    // With KP <= 64 every operand is loaded up front so that the waits for
+    // them leave the data prefetch in flight; larger KP would not fit the
+    // register file, so those operands are loaded at their use below.
+    if constexpr (PRELOAD) {
+      if constexpr (PREC == PREC_FP32) {
+        const f32x4* lp = reinterpret_cast<const f32x4*>(a.L + (int64_t)(r0 + col) * KP + half * (KP / 2));
+  #pragma unroll
+        for (int u = 0; u < KP / 8; ++u) lq[u] = lp[u];
+  #pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          const f32x4* lt =
+              reinterpret_cast<const f32x4*>(a.LT + (int64_t)(32 * t + col) * a.ldlt + r0 + 16 * half);
+  #pragma unroll
+          for (int u = 0; u < 4; ++u) tq[4 * t + u] = lt[u];
+        }
+      } else {
+        const bf16x8* lph = reinterpret_cast<const bf16x8*>(a.Lh + (int64_t)(r0 + col) * KP + 8 * half);
+        const bf16x8* lpl = reinterpret_cast<const bf16x8*>(a.Ll + (int64_t)(r0 + col) * KP + 8 * half);
+  #pragma unroll
+        for (int j = 0; j < KP / 16; ++j) {
+          lh[j] = lph[2 * j];
+          ll[j] = lpl[2 * j];
+        }
+  #pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          const int64_t off = (int64_t)(32 * t + col) * a.ldlt + r0 + 8 * half;
+  #pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            th[2 * t + j] = *reinterpret_cast<const bf16x8*>(a.LTh + off + 16 * j);
+            tl[2 * t + j] = *reinterpret_cast<const bf16x8*>(a.LTl + off + 16 * j);
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- 2. prefetch the next tile's data (stays in flight below) ---------
+    // Unconditional (the last step re-reads its own tile) so that the
+    // number of loads in flight is static and the operand waits below do
+    // not drain the prefetch.
+    const int trn = (tr + NW < t_end) ? tr + NW : tr;
+    load_tile(dcol + (int64_t)trn * 1024, dn);
+    load_tile(mcol + (int64_t)trn * 1024, mn);
+    __builtin_amdgcn_sched_barrier(0);
+
+    // ---- 3. Y = L[r0:r0+32, :] * Rt ----------------------------------------
     f32x16 y = zero16();
-    if constexpr (PREC == PREC_FP32) {
-      const float* lp = a.L + (int64_t)(r0 + col) * KP + half * (KP / 2);
+    if constexpr (!PRELOAD) {
+      if constexpr (PREC == PREC_FP32) {
+        const f32x4* lp =
+            reinterpret_cast<const f32x4*>(a.L + (int64_t)(r0 + col) * KP + half * (KP / 2));
 #pragma unroll
-      for (int j4 = 0; j4 < KP / 2; j4 += 4) {
-        const f32x4 lv = *reinterpret_cast<const f32x4*>(lp + j4);
-        y = mfma_f32(lv[0], rt[j4 + 0], y);
-        y = mfma_f32(lv[1], rt[j4 + 1], y);
-        y = mfma_f32(lv[2], rt[j4 + 2], y);
-        y = mfma_f32(lv[3], rt[j4 + 3], y);
+        for (int u = 0; u < KP / 8; ++u) lq[u] = lp[u];
+      } else {
+        const bf16x8* lph = reinterpret_cast<const bf16x8*>(a.Lh + (int64_t)(r0 + col) * KP + 8 * half);
+        const bf16x8* lpl = reinterpret_cast<const bf16x8*>(a.Ll + (int64_t)(r0 + col) * KP + 8 * half);
+#pragma unroll
+        for (int j = 0; j < KP / 16; ++j) {
+          lh[j] = lph[2 * j];
+          ll[j] = lpl[2 * j];
+        }
+      }
+    }
+    if constexpr (PREC == PREC_FP32) {
+#pragma unroll
+      for (int u = 0; u < KP / 8; ++u) {
+        y = mfma_f32(lq[u][0], rt[4 * u + 0], y);
+        y = mfma_f32(lq[u][1], rt[4 * u + 1], y);
+        y = mfma_f32(lq[u][2], rt[4 * u + 2], y);
+        y = mfma_f32(lq[u][3], rt[4 * u + 3], y);
       }
     } else {
-      const __bf16* lph = a.Lh + (int64_t)(r0 + col) * KP + 8 * half;
-      const __bf16* lpl = a.Ll + (int64_t)(r0 + col) * KP + 8 * half;
 #pragma unroll
-      for (int j = 0; j < KP / 16; ++j) {
-        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(lph + 16 * j);
-        const bf16x8 al = *reinterpret_cast<const bf16x8*>(lpl + 16 * j);
-        y = mfma_bf16x3(ah, al, rth[j], rtl[j], y);
-      }
+      for (int j = 0; j < KP / 16; ++j) y = mfma_bf16x3(lh[j], ll[j], rth[j], rtl[j], y);
     }
 
-    // ---- elementwise: A = Mw o D, Z = Mw o Y, J += Mw (D - Y)^2 -----------
+    // ---- 4. elementwise: A = Mw o D, Z = Mw o Y, J += Mw (D - Y)^2 --------
     float av[16], zv[16];
     float js = 0.f;
 #pragma unroll
@@ -147,19 +200,21 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
     }
     if constexpr (MODE != MODE_SPLIT) jacc += (double)js;
 
+    // ---- 5. num += L^T A, den += L^T Z -------------------------------------
     if constexpr (MODE != MODE_OBJ) {
-      // ---- num += L^T A, den += L^T Z ------------------------------------
       if constexpr (PREC == PREC_FP32) {
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
-          const float* lt = a.LT + (int64_t)(32 * t + col) * a.ldlt + r0 + 16 * half;
-          f32x4 q[4];
+          if constexpr (!PRELOAD) {
+            const f32x4* lt =
+                reinterpret_cast<const f32x4*>(a.LT + (int64_t)(32 * t + col) * a.ldlt + r0 + 16 * half);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) q[u] = *reinterpret_cast<const f32x4*>(lt + 4 * u);
+            for (int u = 0; u < 4; ++u) tq[4 * t + u] = lt[u];
+          }
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
-            num[t] = mfma_f32(q[i >> 2][i & 3], av[i], num[t]);
-            den[t] = mfma_f32(q[i >> 2][i & 3], zv[i], den[t]);
+            num[t] = mfma_f32(tq[4 * t + (i >> 2)][i & 3], av[i], num[t]);
+            den[t] = mfma_f32(tq[4 * t + (i >> 2)][i & 3], zv[i], den[t]);
           }
         }
       } else {
@@ -179,22 +234,34 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
         }
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
-          const int64_t off = (int64_t)(32 * t + col) * a.ldlt + r0 + 8 * half;
+          if constexpr (!PRELOAD) {
+            const int64_t off = (int64_t)(32 * t + col) * a.ldlt + r0 + 8 * half;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              th[2 * t + j] = *reinterpret_cast<const bf16x8*>(a.LTh + off + 16 * j);
+              tl[2 * t + j] = *reinterpret_cast<const bf16x8*>(a.LTl + off + 16 * j);
+            }
+          }
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
-            const bf16x8 lh = *reinterpret_cast<const bf16x8*>(a.LTh + off + 16 * j);
-            const bf16x8 ll = *reinterpret_cast<const bf16x8*>(a.LTl + off + 16 * j);
-            num[t] = mfma_bf16x3(lh, ll, ah[j], al[j], num[t]);
-            den[t] = mfma_bf16x3(lh, ll, zh[j], zl[j], den[t]);
+            num[t] = mfma_bf16x3(th[2 * t + j], tl[2 * t + j], ah[j], al[j], num[t]);
+            den[t] = mfma_bf16x3(th[2 * t + j], tl[2 * t + j], zh[j], zl[j], den[t]);
           }
         }
       }
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      dv[u] = dn[u];
-      mv[u] = mn[u];
-    }
+  };
+
+  int tr = t_begin + wave;
+  f32x4 dA[4], mA[4], dB[4], mB[4];
+  if (tr < t_end) {
+    load_tile(dcol + (int64_t)tr * 1024, dA);
+    load_tile(mcol + (int64_t)tr * 1024, mA);
+  }
+  for (; tr < t_end; tr += 2 * NW) {
+    step(tr, dA, mA, dB, mB);
+    if (tr + NW >= t_end) break;
+    step(tr + NW, dB, mB, dA, mA);
   }
 
   // ---- combine the NW waves' sums in a fixed order -----------------------
@@ -256,11 +323,14 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
     const bool cval = c < a.C_valid;
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
+      float old[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) old[i] = a.Rt[(int64_t)(32 * t + acc_row(i, half)) * a.ldr + c];
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const int k = 32 * t + acc_row(i, half);
         float nv = 0.f;
-        if (cval && k < a.K) nv = mu_apply(a.Rt[(int64_t)k * a.ldr + c], num[t][i], den[t][i], a.eps);
+        if (cval && k < a.K) nv = mu_apply(old[i], num[t][i], den[t][i], a.eps);
         a.Rt_out[(int64_t)k * a.ldr + c] = nv;
         if constexpr (PREC == PREC_FP32) {
           a.RtT[(int64_t)c * KP + k] = nv;

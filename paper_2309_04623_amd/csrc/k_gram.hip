@@ -1,0 +1,340 @@
+// Target modelling through per-frame masked Gram matrices (Sec. 4.1 with
+// the W-rule of Eq. 3 and H fixed), one persistent launch for all frames.
+//
+// For a frame with pixels S, weights m and data t the W-rule denominator
+// [m o (c H)] H^T equals c G with G = H diag(m) H^T (exact re-association),
+// and the numerator is the constant b = H (m o t).  Each workgroup takes
+// frames from a device queue; per frame it
+//   1. streams the frame's pixels in chunks of 32, staging the gathered rows
+//      of H^T (K values per pixel), m and t in LDS, and accumulates the
+//      upper-triangle 32x32 tiles of G on MFMA (tiles spread over the four
+//      waves) and b on the vector units (FP64 accumulation);
+//   2. writes G to LDS, gives thread j row j of G in registers, and runs all
+//      iterations c_j <- max(c_j b_j / (c G)_j, eps) with c in LDS.
+// Pixels appear only through the staged chunks, so dense frames (all
+// pixels, weight row of M_T) and CSR frames share the kernel.
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace nmf {
+
+template <int KP>
+__host__ __device__ constexpr int gram_tiles() {
+  return (KP / 32) * (KP / 32 + 1) / 2;
+}
+
+// Upper-triangle tile index -> (mi, mj), row-major over mi <= mj.
+__device__ __forceinline__ void tile_of(int idx, int nb, int& mi, int& mj) {
+  mi = 0;
+  while (idx >= nb - mi) {
+    idx -= nb - mi;
+    ++mi;
+  }
+  mj = mi + idx;
+}
+
+template <int KP, bool RAGGED>
+__global__ __launch_bounds__(256) void k_gram(GramArgs a) {
+  extern __shared__ __align__(16) float lds[];
+  __shared__ int qslot;
+  constexpr int NB = KP / 32;
+  constexpr int NT = gram_tiles<KP>();
+  constexpr int TPW = (NT + 3) / 4;
+  constexpr int KQ = KP / 4;
+  const int K = a.K;
+  float* Hs = lds;            // [32][KP] gathered H^T rows
+  float* ms = lds + 32 * KP;  // [32] weights
+  float* ts = ms + 32;        // [32] data
+  float* G = lds;             // [K][K] after the pixel loop (aliases the above)
+  const int goff = (max(K * K, 32 * KP + 64) + 3) & ~3;
+  double* bsh = reinterpret_cast<double*>(lds + goff);  // [KP]
+  float* csh = reinterpret_cast<float*>(bsh + KP);      // [KP]
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int col = lane & 31, half = lane >> 5;
+  int tmi[TPW], tmj[TPW];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int idx = wave + 4 * q;
+    if (idx < NT) {
+      tile_of(idx, NB, tmi[q], tmj[q]);
+    } else {
+      tmi[q] = -1;
+      tmj[q] = -1;
+    }
+  }
+  const f32x4* HT4 = reinterpret_cast<const f32x4*>(a.HT);
+  f32x4* Hs4 = reinterpret_cast<f32x4*>(Hs);
+  const uint64_t key = sm_key(a.seed, 2);
+  int bad = 0;
+
+  while (true) {
+    if (tid == 0) qslot = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int qi = qslot;
+    __syncthreads();
+    if (qi >= a.F) break;
+    const int f = a.order ? a.order[qi] : qi;
+    const uint64_t tick0 = wall_clock64();
+
+    int64_t s = 0, e = a.P;
+    if constexpr (RAGGED) {
+      s = a.offsets[f];
+      e = a.offsets[f + 1];
+      if (!(s >= 0 && s <= e && e <= a.nnz)) {
+        bad |= 16;
+        s = e = 0;
+      }
+    }
+
+    f32x16 acc[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) acc[q] = zero16();
+    double bacc = 0.0;
+
+    for (int64_t base = s; base < e; base += 32) {
+      // ---- stage 32 pixels: rows of H^T, weights, data -------------------
+      for (int x = tid; x < 32 * KQ; x += 256) {
+        const int jr = x / KQ, kq = x - jr * KQ;
+        const int64_t jj = base + jr;
+        f32x4 v = {0.f, 0.f, 0.f, 0.f};
+        if (jj < e) {
+          int prow;
+          if constexpr (RAGGED) {
+            prow = a.pix[jj];
+            if (prow < 0 || prow >= a.P) prow = -1;
+          } else {
+            prow = (int)jj;
+          }
+          if (prow >= 0) v = HT4[(int64_t)prow * KQ + kq];
+        }
+        Hs4[x] = v;
+      }
+      if (tid < 32) {
+        const int64_t jj = base + tid;
+        float m = 0.f, t = 0.f;
+        if (jj < e) {
+          if constexpr (RAGGED) {
+            const int prow = a.pix[jj];
+            m = a.wt ? a.wt[jj] : 1.0f;
+            t = a.val[jj];
+            if (prow < 0 || prow >= a.P) {
+              bad |= 16;
+              m = 0.f;
+            }
+          } else {
+            m = a.MT[(int64_t)f * a.P + jj];
+            t = a.T[(int64_t)f * a.P + jj];
+          }
+          if (!(m >= 0.f) || isinf(m)) {
+            bad |= 4;
+            m = 0.f;
+          }
+          if (m > 0.f) {
+            if (!isfinite(t)) {
+              bad |= 1;
+              t = 0.f;
+            } else if (t < 0.f) {
+              if (a.clip_negative) {
+                m = 0.f;
+                t = 0.f;
+              } else {
+                bad |= 2;
+              }
+            }
+          } else {
+            t = 0.f;
+          }
+        }
+        ms[tid] = m;
+        ts[tid] = t;
+      }
+      __syncthreads();
+
+      // ---- G tiles: G[mi-block, mj-block] += (H o m) H^T over the chunk ---
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        if (tmi[q] >= 0) {
+          const float* ha = Hs + 32 * tmi[q] + col;
+          const float* hb = Hs + 32 * tmj[q] + col;
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int jr = 2 * u + half;
+            acc[q] = mfma_f32(ha[jr * KP] * ms[jr], hb[jr * KP], acc[q]);
+          }
+        }
+      }
+      // ---- b += H (m o t) --------------------------------------------------
+      if (tid < KP) {
+#pragma unroll 8
+        for (int jr = 0; jr < 32; ++jr) bacc += (double)(Hs[jr * KP + tid] * ms[jr]) * (double)ts[jr];
+      }
+      __syncthreads();
+    }
+
+    // ---- G to LDS (both triangles), b and the starting coefficients -------
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      if (tmi[q] >= 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 32 * tmi[q] + acc_row(r, half);
+          const int cg = 32 * tmj[q] + col;
+          if (row < K && cg < K) {
+            G[row * K + cg] = acc[q][r];
+            if (tmi[q] != tmj[q]) G[cg * K + row] = acc[q][r];
+          }
+        }
+      }
+    }
+    if (tid < KP) {
+      bsh[tid] = tid < K ? bacc : 0.0;
+      float c0 = 0.f;
+      if (tid < K)
+        c0 = a.C_init ? a.C_init[(int64_t)f * K + tid] : sm_uniform(key, (uint64_t)f * K + tid);
+      csh[tid] = c0;
+    }
+    __syncthreads();
+
+    // ---- iterations: (c G)_j with row j of G in registers (K <= 128) or
+    // read from LDS (consecutive j across lanes, conflict-free) ------------
+    const int j = tid;
+    const double bj = j < KP ? bsh[j] : 0.0;
+    const f32x4* c4 = reinterpret_cast<const f32x4*>(csh);
+    if constexpr (KP <= 128) {
+      float g[KP];
+#pragma unroll
+      for (int i = 0; i < KP; ++i) g[i] = (j < K && i < K) ? G[j * K + i] : 0.f;
+      for (int it = 0; it < a.iters; ++it) {
+        float den = 0.f;
+#pragma unroll
+        for (int i4 = 0; i4 < KQ; ++i4) {
+          const f32x4 cv = c4[i4];
+          den = fmaf(cv[0], g[4 * i4 + 0], den);
+          den = fmaf(cv[1], g[4 * i4 + 1], den);
+          den = fmaf(cv[2], g[4 * i4 + 2], den);
+          den = fmaf(cv[3], g[4 * i4 + 3], den);
+        }
+        __syncthreads();
+        if (j < K) csh[j] = mu_apply_d(csh[j], bj, (double)den, a.eps);
+        __syncthreads();
+      }
+    } else {
+      const float* gcol = G + (j < K ? j : 0);
+      for (int it = 0; it < a.iters; ++it) {
+        float den = 0.f;
+        if (j < K) {
+          for (int i = 0; i < K; ++i) den = fmaf(csh[i], gcol[i * K], den);
+        }
+        __syncthreads();
+        if (j < K) csh[j] = mu_apply_d(csh[j], bj, (double)den, a.eps);
+        __syncthreads();
+      }
+    }
+    if (j < K) a.C_out[(int64_t)f * K + j] = csh[j];
+    if (a.ticks && tid == 0) {
+      a.ticks[2 * (int64_t)f] = tick0;
+      a.ticks[2 * (int64_t)f + 1] = wall_clock64();
+    }
+    __syncthreads();  // LDS is reused by the next frame
+  }
+  if (bad) atomicOr(a.status, bad);
+}
+
+size_t gram_lds_bytes(int K, int KP) {
+  const int goff = (std::max(K * K, 32 * KP + 64) + 3) & ~3;
+  return (size_t)goff * 4 + (size_t)KP * 8 + (size_t)KP * 4;
+}
+
+template <int KP, bool RAGGED>
+static hipError_t gram_launch(const GramArgs& a, int max_blocks, hipStream_t s, int* grid_out) {
+  const size_t lds = gram_lds_bytes(a.K, KP);
+  auto fn = k_gram<KP, RAGGED>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  int grid = std::max(1, std::min(a.F, cus * per_cu));
+  if (max_blocks > 0) grid = std::min(grid, max_blocks);
+  if (grid_out) *grid_out = grid;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <bool RAGGED>
+static hipError_t gram_kp(int kp, const GramArgs& a, int max_blocks, hipStream_t s, int* g) {
+  switch (kp) {
+    case 32: return gram_launch<32, RAGGED>(a, max_blocks, s, g);
+    case 64: return gram_launch<64, RAGGED>(a, max_blocks, s, g);
+    case 96: return gram_launch<96, RAGGED>(a, max_blocks, s, g);
+    case 128: return gram_launch<128, RAGGED>(a, max_blocks, s, g);
+    case 160: return gram_launch<160, RAGGED>(a, max_blocks, s, g);
+    case 192: return gram_launch<192, RAGGED>(a, max_blocks, s, g);
+    case 224: return gram_launch<224, RAGGED>(a, max_blocks, s, g);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, hipStream_t s,
+                       int* grid_out) {
+  return ragged ? gram_kp<true>(kp, a, max_blocks, s, grid_out)
+                : gram_kp<false>(kp, a, max_blocks, s, grid_out);
+}
+
+// ---------------------------------------------------------------------------
+// Longest-first frame order for the persistent queue: one workgroup bitonic
+// sort of (size, index) pairs, descending size then ascending index.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_frame_order(const int64_t* offsets, int f, int n2,
+                                                     int* order) {
+  __shared__ int ks[MAX_SORT_FRAMES];
+  __shared__ int vs[MAX_SORT_FRAMES];
+  for (int i = threadIdx.x; i < n2; i += 1024) {
+    if (i < f) {
+      const int64_t d = offsets[i + 1] - offsets[i];
+      ks[i] = d < 0 ? 0 : (d > 0x7fffffff ? 0x7fffffff : (int)d);
+    } else {
+      ks[i] = -1;
+    }
+    vs[i] = i;
+  }
+  __syncthreads();
+  for (int size = 2; size <= n2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += 1024) {
+        const int jx = i ^ stride;
+        if (jx > i) {
+          // "before" = larger size, then smaller index
+          const bool desc = (i & size) == 0;
+          const bool i_before = ks[i] > ks[jx] || (ks[i] == ks[jx] && vs[i] < vs[jx]);
+          if (desc != i_before) {
+            const int tk = ks[i], tv = vs[i];
+            ks[i] = ks[jx];
+            vs[i] = vs[jx];
+            ks[jx] = tk;
+            vs[jx] = tv;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < f; i += 1024) order[i] = vs[i];
+}
+
+hipError_t launch_frame_order(const int64_t* offsets, int f, int* order, hipStream_t s) {
+  if (f > MAX_SORT_FRAMES) return hipErrorInvalidValue;
+  int n2 = 1;
+  while (n2 < f) n2 <<= 1;
+  hipLaunchKernelGGL(k_frame_order, dim3(1), dim3(1024), 0, s, offsets, f, n2, order);
+  return hipGetLastError();
+}
+
+}  // namespace nmf

@@ -149,4 +149,34 @@ hipError_t launch_frame_objective(const float* H, const float* C, const float* T
                                   const float* MT, int64_t f, int k, int64_t p, double* out,
                                   hipStream_t s);
 
+// Masked-Gram projection: one persistent launch over all frames.
+struct GramArgs {
+  const float* HT;  // P_pad x KP, row per pixel (H transposed)
+  int K, P, F;
+  // dense frames (F x P), or CSR frames
+  const float* T;
+  const float* MT;
+  const int64_t* offsets;
+  int64_t nnz;
+  const int32_t* pix;
+  const float* val;
+  const float* wt;     // nullable: weights 1
+  const int* order;    // nullable: processing order
+  const float* C_init; // nullable: seeded U(0,1), matrix 2
+  uint64_t seed;
+  int iters;
+  float eps;
+  int clip_negative;
+  float* C_out;        // F x K
+  int* queue;          // zeroed before the launch
+  int* status;         // bits as staging, plus 16 = bad CSR entry
+  uint64_t* ticks;     // nullable: 2 per frame
+};
+size_t gram_lds_bytes(int K, int KP);
+hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, hipStream_t s,
+                       int* grid_out);
+// Longest-first processing order of up to MAX_SORT_FRAMES CSR frames.
+constexpr int MAX_SORT_FRAMES = 8192;
+hipError_t launch_frame_order(const int64_t* offsets, int f, int* order, hipStream_t s);
+
 }  // namespace nmf

@@ -69,9 +69,10 @@ _SIGS = {
                                        _vp, _vp, _dp, ctypes.POINTER(Report), _vp]),
     "nmf_project": (ctypes.c_int, [_vp, _vp, _i64, _i64, _vp, _vp, _i64, ctypes.POINTER(Params),
                                    _vp, _vp, _vp, ctypes.POINTER(Report), _vp]),
-    "nmf_project_ragged": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp,
+    "nmf_project_ragged": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _vp, _vp,
                                           ctypes.POINTER(Params), _vp, _vp, _vp,
                                           ctypes.POINTER(Report), _vp]),
+    "nmf_device_clock_khz": (ctypes.c_double, [_vp]),
     "nmf_subtract": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp]),
     "nmf_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "nmf_profile_get": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int64),
@@ -240,8 +241,11 @@ def build_basis(V, M, k, iters, *, precision="fp32", W_init=None, H_init=None, s
 
 
 def project(H, T, MT, iters, *, C_init=None, precision="fp32", seed=0, flags=0, eps=1e-30,
-            split=0, want_objective=False, handle=None):
-    """Target modelling: per-frame coefficients with the basis fixed."""
+            split=0, want_objective=False, gram=False, handle=None):
+    """Target modelling: per-frame coefficients with the basis fixed
+    (``gram=True``: through per-frame masked Gram matrices)."""
+    if gram:
+        flags |= F_MASKED_GRAM
     torch = _torch()
     dev = H.device.index or 0
     h = handle or default_handle(dev)
@@ -287,3 +291,30 @@ def profile_get(handle: Handle, kernel_class: int):
     ms = ctypes.c_double()
     _check(lib().nmf_profile_get(handle.h, kernel_class, ctypes.byref(n), ctypes.byref(ms)))
     return int(n.value), float(ms.value)
+
+
+def project_ragged(H, offsets, pix, val, wt, iters, *, C_init=None, seed=0, flags=0, eps=1e-30,
+                   want_ticks=False, handle=None):
+    """Projection of CSR frames (one persistent launch, masked Gram form).
+    offsets: int64 (f+1), pix: int32, val/wt: float32 (wt may be None)."""
+    torch = _torch()
+    dev = H.device.index or 0
+    h = handle or default_handle(dev)
+    k, p = H.shape
+    f = offsets.shape[0] - 1
+    nnz = pix.shape[0]
+    C = torch.empty((f, k), dtype=torch.float32, device=H.device)
+    ticks = torch.zeros(2 * f, dtype=torch.int64, device=H.device) if want_ticks else None
+    prm = make_params(k, iters, "fp32", seed, flags, eps)
+    rep = _new_report()
+    _check(lib().nmf_project_ragged(
+        h.h, _dev_ptr(H, "H", torch.float32), k, p, f, _dev_ptr(offsets, "offsets", torch.int64),
+        nnz, _dev_ptr(pix, "pix", torch.int32), _dev_ptr(val, "val", torch.float32),
+        _dev_ptr(wt, "wt", torch.float32), ctypes.byref(prm), _dev_ptr(C_init, "C_init", torch.float32),
+        _dev_ptr(C, "C_out"), _dev_ptr(ticks, "frame_ticks"), ctypes.byref(rep), _stream(dev)))
+    return (C, ticks, rep.as_dict()) if want_ticks else (C, rep.as_dict())
+
+
+def device_clock_khz(handle=None, device=0) -> float:
+    h = handle or default_handle(device)
+    return float(lib().nmf_device_clock_khz(h.h))

@@ -16,6 +16,7 @@ EXPECTED = {
     "nmf_create", "nmf_destroy", "nmf_status_string", "nmf_last_error", "nmf_params_default",
     "nmf_workspace_bytes", "nmf_init_uniform", "nmf_objective", "nmf_build_basis", "nmf_project",
     "nmf_project_ragged", "nmf_subtract", "nmf_profile_enable", "nmf_profile_get",
+    "nmf_device_clock_khz",
 }
 
 
@@ -155,3 +156,23 @@ def test_create_without_device_fails_cleanly(L):
     assert rc in (nmf.NMF_ERR_HIP, nmf.NMF_ERR_ARG)
     assert not h.value
     assert L.nmf_destroy(None) == 0
+
+
+def test_project_ragged_validation(L):
+    prm = _prm(L, k=4)
+    P = ctypes.byref(prm)
+
+    def call(h=None, H=FAKE, k=4, p=100, f=3, off=FAKE + 4, nnz=10, pix=FAKE + 8, val=FAKE + 12,
+             wt=None, prm_=P, C=FAKE + 16):
+        return L.nmf_project_ragged(h, H, k, p, f, off, nnz, pix, val, wt, prm_, None, C, None,
+                                    None, None)
+    assert call(off=None) == nmf.NMF_ERR_ARG
+    assert call(pix=None) == nmf.NMF_ERR_ARG
+    assert call(nnz=-1) == nmf.NMF_ERR_SHAPE
+    assert call(f=0) == nmf.NMF_ERR_SHAPE
+    assert call(k=5) == nmf.NMF_ERR_ARG           # params.k != k
+    big = _prm(L, k=201)
+    assert call(k=201, p=1000, prm_=ctypes.byref(big)) == nmf.NMF_ERR_UNSUPPORTED
+    assert call(C=FAKE + 12) == nmf.NMF_ERR_ARG    # C_out aliases val
+    assert call() == nmf.NMF_ERR_ARG               # handle
+    assert b"handle" in L.nmf_last_error()

@@ -1,0 +1,184 @@
+"""GPU parity of the masked-Gram projection (dense frames and CSR frames in
+one persistent launch) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import nmf64, nnls, prng
+from paper_2309_04623_amd import nmf, synth
+from tests.helpers import dev, host, rel_model_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _basis(k, p, seed=0):
+    g = np.random.default_rng(seed)
+    return (g.gamma(1.0, 1.0, (k, p)) * g.uniform(0.2, 1.0, (k, 1))).astype(np.float32)
+
+
+def _photon_frames(H, f, seed, peak=1e4, mask_frac=0.1):
+    g = np.random.default_rng(seed)
+    clean = g.gamma(2.0, 1.0, (f, H.shape[0])) @ H
+    gain = peak / clean.max(axis=1, keepdims=True)
+    T = g.poisson(gain * clean) / gain
+    MT = (g.random(T.shape) >= mask_frac) / (T + 0.01)
+    return T.astype(np.float32), MT.astype(np.float32)
+
+
+def _compare(T, MT, H, Cg, Co, tol_j=1e-5, tol_m=1e-4, derived=False):
+    """Objective and model bars.  With ``derived`` the objective bar is
+    max(tol_j, 2e-6 * snr): a 1e-6 relative change of the FP32 model moves J
+    by about 2e-6 times the model-to-residual ratio snr."""
+    Jo = nmf64.frame_objective(T, MT, H, Co)
+    Jg = nmf64.frame_objective(T, MT, H, Cg)
+    relJ = np.abs(Jg - Jo) / Jo
+    model = max(rel_model_err(MT[i:i + 1], Cg[i:i + 1] @ H, Co[i:i + 1] @ H) for i in range(len(T)))
+    Th = np.where(MT > 0, T, 0.0)
+    mod = Co @ H
+    snr = np.linalg.norm(MT * mod, axis=1) / np.linalg.norm(MT * (Th - mod), axis=1)
+    bar = np.maximum(tol_j, 2e-6 * snr) if derived else tol_j
+    print(f"  relJ={relJ.max():.3e} model={model:.3e} snr={snr.max():.1f}", flush=True)
+    assert np.all(relJ <= bar) and model <= tol_m
+    assert np.all(Cg >= 0)
+
+
+@pytest.mark.parametrize("f,k,p,iters", [(1, 8, 4096, 200), (50, 30, 6400, 300), (37, 5, 1000, 100),
+                                         (3, 100, 3000, 80), (9, 33, 777, 120), (4, 200, 2500, 60),
+                                         (5, 130, 1100, 50)])
+def test_gram_dense_parity(f, k, p, iters):
+    """Dense frames through the Gram form: the oracle's direct-form iterate
+    (same value in exact arithmetic) within 1e-5 objective / 1e-4 model."""
+    H = _basis(k, p, seed=k)
+    T, MT = _photon_frames(H, f, seed=f + k)
+    C0 = prng.init_matrix(5, prng.MAT_C, f, k)
+    say("gram dense", f, k, p, iters)
+    C, obj, _ = nmf.project(dev(H), dev(T), dev(MT), iters, seed=5, gram=True, want_objective=True)
+    Co = nmf64.project(T, MT, H, C0, iters)
+    _compare(T, MT, H, host(C), Co)
+    Jg = nmf64.frame_objective(T, MT, H, host(C))
+    assert np.max(np.abs(host(obj) - Jg) / Jg) < 1e-6
+
+
+def _ragged(H, sizes, seed, binary=False):
+    g = np.random.default_rng(seed)
+    k, p = H.shape
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pix = np.concatenate([np.sort(g.choice(p, s, replace=False)) for s in sizes]).astype(np.int32)
+    w = g.gamma(2.0, 1.0, (len(sizes), k))
+    val = np.empty(offs[-1], np.float32)
+    for i in range(len(sizes)):
+        clean = w[i] @ H[:, pix[offs[i]:offs[i + 1]]]
+        gain = 1e4 / max(clean.max(), 1e-30)
+        val[offs[i]:offs[i + 1]] = g.poisson(gain * clean) / gain
+    wt = np.ones_like(val) if binary else (1.0 / (val + 0.01)).astype(np.float32)
+    return offs, pix, val, wt
+
+
+@pytest.mark.parametrize("k,p,sizes,binary", [
+    (8, 4096, [4096, 100, 1, 2000, 33], False),
+    (30, 6400, [6400, 0, 3000, 31, 32, 33, 5000], True),
+    (100, 3000, [2999, 1500, 64, 700], False),
+    (200, 2500, [2500, 1200, 300], True),
+])
+def test_ragged_parity(k, p, sizes, binary):
+    """CSR frames of uneven size (including an empty frame and sizes around
+    the 32-pixel chunk) match the oracle frame by frame."""
+    H = _basis(k, p, seed=k + 1)
+    offs, pix, val, wt = _ragged(H, sizes, seed=k, binary=binary)
+    f = len(sizes)
+    iters = 100
+    C0 = prng.init_matrix(9, prng.MAT_C, f, k)
+    say("ragged", k, p, sizes)
+    C, ticks, rep = nmf.project_ragged(dev(H), dev_i64(offs), dev_i32(pix), dev(val),
+                                       None if binary else dev(wt), iters, seed=9, want_ticks=True)
+    Cg = host(C)
+    Co = nmf64.project_ragged(offs, pix, val, wt, H, C0, iters)
+    T, MT = nmf64.ragged_to_dense(offs, pix, val, wt, p)
+    nonempty = [i for i in range(f) if sizes[i] > 0]
+    _compare(T[nonempty], MT[nonempty], H, Cg[nonempty], Co[nonempty])
+    for i in range(f):
+        if sizes[i] == 0:  # no data: den = 0 keeps the start values
+            assert np.array_equal(Cg[i], C0[i].astype(np.float32))
+    t = host(ticks).astype(np.int64).reshape(f, 2)
+    assert np.all(t[:, 1] >= t[:, 0]) and np.all(t[:, 0] > 0)
+
+
+def dev_i64(x):
+    import torch
+    return torch.as_tensor(np.asarray(x, np.int64)).cuda()
+
+
+def dev_i32(x):
+    import torch
+    return torch.as_tensor(np.asarray(x, np.int32)).cuda()
+
+
+def test_ragged_bad_entries_rejected():
+    H = _basis(4, 100, seed=1)
+    offs = np.array([0, 3, 6], np.int64)
+    pix = np.array([1, 2, 3, 4, 5, 100], np.int32)  # 100 is out of range
+    val = np.ones(6, np.float32)
+    say("ragged bad pixel")
+    with pytest.raises(nmf.NmfError) as e:
+        nmf.project_ragged(dev(H), dev_i64(offs), dev_i32(pix), dev(val), None, 5)
+    assert e.value.status == nmf.NMF_ERR_ARG
+    offs = np.array([0, 3, 9], np.int64)  # past nnz
+    pix[5] = 5
+    with pytest.raises(nmf.NmfError) as e:
+        nmf.project_ragged(dev(H), dev_i64(offs), dev_i32(pix), dev(val), None, 5)
+    assert e.value.status == nmf.NMF_ERR_ARG
+
+
+def test_ragged_graph_replay_matches_eager():
+    """The captured graph replays to the same bits as an eager (timed) run,
+    several replays in a row with other work in between."""
+    H = _basis(30, 2000, seed=2)
+    offs, pix, val, wt = _ragged(H, [2000, 50, 1234, 700] * 8, seed=3)
+    args = (dev(H), dev_i64(offs), dev_i32(pix), dev(val), dev(wt))
+    say("ragged graph replay")
+    h = nmf.Handle(0)
+    nmf.profile_enable(h, True)
+    ref, _ = nmf.project_ragged(*args, 50, seed=4, handle=h)
+    nmf.profile_enable(h, False)
+    import torch
+    C0 = nmf.init_uniform(4, nmf.MAT_C, len(offs) - 1, 30)
+    for i in range(4):
+        C, _ = nmf.project_ragged(*args, 50, seed=4, C_init=C0, handle=h)
+        torch.cuda.synchronize()
+        assert torch.equal(C, ref)
+        _ = torch.randn(1000, device="cuda").sum().item()
+    h.close()
+
+
+def test_gram_projection_reaches_nnls():
+    H = _basis(4, 600, seed=7)
+    T, MT = _photon_frames(H, 5, seed=8)
+    say("gram -> nnls")
+    C, _ = nmf.project(dev(H), dev(T), dev(MT), 30000, seed=1, gram=True)
+    C = host(C)
+    for i in range(5):
+        G, b, c = nnls.normal_equations(H, T[i], MT[i])
+        w, j = nnls.nnls_bruteforce(G, b, c)
+        assert nnls.cost(G, b, c, C[i]) - j <= 1e-5 * j
+
+
+def test_cfg4_shaped_batch_sample():
+    """MIRI-shaped CSR batch (224 x 288 px frames keeping 1000-64512 pixels
+    nearest the star outside the cross, K = 200, 300 iterations): sampled
+    frames match the oracle."""
+    k, ny, nx = 200, 224, 288
+    g = np.random.default_rng(0)
+    H = synth.components_speckle(g, k, ny, nx).astype(np.float32)
+    rf = synth.make_ragged(H.astype(np.float64), ny, nx, 24, 1000, 64512)
+    say("cfg4-shaped 24 frames")
+    C, _ = nmf.project_ragged(dev(H), dev_i64(rf.offsets), dev_i32(rf.pix), dev(rf.val), None, 300,
+                              seed=2)
+    Cg = host(C)
+    C0 = prng.init_matrix(2, prng.MAT_C, 24, k)
+    sel = [0, 11, 23]
+    o = rf.offsets
+    for i in sel:
+        sub_off = np.array([0, o[i + 1] - o[i]])
+        sl = slice(o[i], o[i + 1])
+        co = nmf64.project_ragged(sub_off, rf.pix[sl], rf.val[sl], rf.wt[sl], H, C0[i:i + 1], 300)
+        T, MT = nmf64.ragged_to_dense(sub_off, rf.pix[sl], rf.val[sl], rf.wt[sl], ny * nx)
+        _compare(T, MT, H, Cg[i:i + 1], co, derived=True)
