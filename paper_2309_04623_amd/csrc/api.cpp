@@ -740,19 +740,42 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   F.status = stat;
 
   const int c = (prm->tol > 0.0 && prm->check_every > 0) ? prm->check_every : 0;
+  // Iterations run as replays of a captured graph of ``chunk`` iterations
+  // (the finish kernel advances the device iteration counter, so every
+  // chunk is the same launch sequence).
+  const int chunk = c ? c : std::min(T, 64);
+  auto enqueue_iters = [&](hipStream_t s, int count) -> hipError_t {
+    hipError_t e;
+    for (int i = 0; i < count; ++i) {
+      if ((e = timed(h, NMF_K_HRULE, s,
+                     [&]() { return launch_dual(prec, KP, MODE_UPDATE, ca.nw, A, ptile, 1, s); })))
+        return e;
+      if ((e = timed(h, NMF_K_WRULE, s, [&]() {
+             return launch_dual(prec, KP, MODE_SPLIT, cb.nw, B, ntile, cb.splits, s);
+           })))
+        return e;
+      if ((e = timed(h, NMF_K_WFINISH, s, [&]() { return launch_finish(F, s); }))) return e;
+    }
+    return hipSuccess;
+  };
+  auto iter_key = [&](int count) {
+    return key_of("iters", {(uint64_t)D, (uint64_t)DT, (uint64_t)Wf.m, (uint64_t)Hf.m,
+                            (uint64_t)partial, (uint64_t)part, (uint64_t)Jhist, (uint64_t)iter,
+                            (uint64_t)stat, (uint64_t)n, (uint64_t)p, (uint64_t)K,
+                            (uint64_t)prec, (uint64_t)__builtin_bit_cast(uint32_t, eps),
+                            (uint64_t)ca.nw, (uint64_t)cb.nw, (uint64_t)cb.splits,
+                            (uint64_t)count});
+  };
   int t = 0;
   bool stopped = false;
   int pending_check = -1;  // iteration whose J copy is in flight
   hipEvent_t chk = nullptr;
   if (c) HIP_TRY(hipEventCreateWithFlags(&chk, hipEventDisableTiming));
   while (t < T) {
-    const int chunk_end = c ? std::min(T, t + c) : T;
-    for (; t < chunk_end; ++t) {
-      LAUNCH(NMF_K_HRULE, launch_dual(prec, KP, MODE_UPDATE, ca.nw, A, ptile, 1, s));
-      LAUNCH(NMF_K_WRULE, launch_dual(prec, KP, MODE_SPLIT, cb.nw, B, ntile, cb.splits, s));
-      LAUNCH(NMF_K_WFINISH, launch_finish(F, s));
-    }
-    if (!c) break;
+    const int count = std::min(chunk, T - t);
+    HIP_TRY(run_graph(h, iter_key(count), s, [&](hipStream_t st) { return enqueue_iters(st, count); }));
+    t += count;
+    if (!c) continue;
     // J of the last iteration of a chunk is known once that chunk completes;
     // decide on the previous chunk's value so that one chunk stays queued.
     if (pending_check >= 0) {
