@@ -279,6 +279,7 @@ int check_params(const nmf_params* prm, int64_t rows, int64_t cols, bool need_k_
   if (prm->split < 0) return fail(NMF_ERR_ARG, "split must be >= 0");
   if (prm->waves != 0 && prm->waves != 1 && prm->waves != 2 && prm->waves != 4)
     return fail(NMF_ERR_ARG, "waves must be 0, 1, 2 or 4");
+  if (prm->pipeline < 0 || prm->pipeline > 2) return fail(NMF_ERR_ARG, "pipeline must be 0, 1 or 2");
   return NMF_OK;
 }
 
@@ -346,6 +347,7 @@ void nmf_params_default(nmf_params* prm) {
   prm->floor_eps = 1e-30f;
   prm->split = 0;
   prm->waves = 0;
+  prm->pipeline = 0;
 }
 
 int nmf_create(int hip_device, nmf_handle* out) {
@@ -419,7 +421,10 @@ struct PassCfg {
   int nw = 1;
   int splits = 1;
   int tiles_per_split = 1;
+  int pipe = 1;
 };
+
+int pipe_for(int KP, int req) { return KP > 64 ? 0 : (req > 0 ? req : 2); }
 
 // Resident waves per SIMD of the fused kernels by padded component count
 // (from their register use).
@@ -442,6 +447,7 @@ PassCfg cfg_whole(int col_tiles, int RT, int KP, int req_nw) {
   }
   c.splits = 1;
   c.tiles_per_split = RT;
+  c.pipe = pipe_for(KP, 0);
   return c;
 }
 
@@ -453,6 +459,7 @@ PassCfg cfg_split(int col_tiles, int RT, int KP, int req_split, int req_nw) {
   S = std::min(S, std::max(1, RT / c.nw));
   c.tiles_per_split = (RT + S - 1) / S;
   c.splits = (RT + c.tiles_per_split - 1) / c.tiles_per_split;
+  c.pipe = pipe_for(KP, 0);
   return c;
 }
 
@@ -641,7 +648,7 @@ int nmf_objective(nmf_handle h, const float* V, const float* M, const float* W, 
   DualArgs a = pass_args(D, Mw, n_pad / 32, p_pad, (int)p, Wf, Hf.t, k, 0.f);
   a.Jpart = part;
   const PassCfg pc = cfg_whole(p_pad / 32, n_pad / 32, KP, 0);
-  LAUNCH(NMF_K_OBJECTIVE, launch_dual(precision, KP, MODE_OBJ, pc.nw, a, p_pad / 32, 1, s));
+  LAUNCH(NMF_K_OBJECTIVE, launch_dual(precision, KP, MODE_OBJ, pc.nw, pc.pipe, a, p_pad / 32, 1, s));
   LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, p_pad / 32, Jdev, nullptr, s));
   int st = 0;
   HIP_TRY(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -679,8 +686,9 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
 
   const int n_pad = round_up(n, 32), p_pad = round_up(p, 32);
   const int ntile = n_pad / 32, ptile = p_pad / 32;
-  const PassCfg ca = cfg_whole(ptile, ntile, KP, prm->waves);
-  const PassCfg cb = cfg_split(ntile, ptile, KP, prm->split, prm->waves);
+  PassCfg ca = cfg_whole(ptile, ntile, KP, prm->waves);
+  PassCfg cb = cfg_split(ntile, ptile, KP, prm->split, prm->waves);
+  ca.pipe = cb.pipe = pipe_for(KP, prm->pipeline);
 
   float *D, *Mw, *DT, *MwT, *partial;
   double *part, *Jhist, *sum_mv2;
@@ -748,10 +756,10 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
     hipError_t e;
     for (int i = 0; i < count; ++i) {
       if ((e = timed(h, NMF_K_HRULE, s,
-                     [&]() { return launch_dual(prec, KP, MODE_UPDATE, ca.nw, A, ptile, 1, s); })))
+                     [&]() { return launch_dual(prec, KP, MODE_UPDATE, ca.nw, ca.pipe, A, ptile, 1, s); })))
         return e;
       if ((e = timed(h, NMF_K_WRULE, s, [&]() {
-             return launch_dual(prec, KP, MODE_SPLIT, cb.nw, B, ntile, cb.splits, s);
+             return launch_dual(prec, KP, MODE_SPLIT, cb.nw, cb.pipe, B, ntile, cb.splits, s);
            })))
         return e;
       if ((e = timed(h, NMF_K_WFINISH, s, [&]() { return launch_finish(F, s); }))) return e;
@@ -801,7 +809,7 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   }
   const int iters_run = t;
   // Objective after the last iteration.
-  LAUNCH(NMF_K_OBJECTIVE, launch_dual(prec, KP, MODE_OBJ, ca.nw, A, ptile, 1, s));
+  LAUNCH(NMF_K_OBJECTIVE, launch_dual(prec, KP, MODE_OBJ, ca.nw, ca.pipe, A, ptile, 1, s));
   LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, ptile, Jhist + iters_run, stat, s));
   if (prm->flags & NMF_F_NORMALIZE_H) LAUNCH(NMF_K_OTHER, launch_normalize(Hf.t, KP, p_pad, K, Wf.t, n_pad, s));
   LAUNCH(NMF_K_OTHER, launch_factor_out(Wf.t, (int)n, n_pad, K, KP, 0, W_out, s));
@@ -893,7 +901,8 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
   hipStream_t s = (hipStream_t)stream;
   const int f_pad = round_up(f, 32), p_pad = round_up(p, 32);
   const int ftile = f_pad / 32, ptile = p_pad / 32;
-  const PassCfg cb = cfg_split(ftile, ptile, KP, prm->split, prm->waves);
+  PassCfg cb = cfg_split(ftile, ptile, KP, prm->split, prm->waves);
+  cb.pipe = pipe_for(KP, prm->pipeline);
   float *DT, *MwT, *partial;
   double* part;
   int* stat;
@@ -924,7 +933,7 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
   B.partial = partial;
   FinishArgs F = finish_args(partial, cb.splits, Cf, (int)f, K, prm->floor_eps, prec);
   for (int it = 0; it < prm->max_iter; ++it) {
-    LAUNCH(NMF_K_PROJECT, launch_dual(prec, KP, MODE_SPLIT, cb.nw, B, ftile, cb.splits, s));
+    LAUNCH(NMF_K_PROJECT, launch_dual(prec, KP, MODE_SPLIT, cb.nw, cb.pipe, B, ftile, cb.splits, s));
     LAUNCH(NMF_K_PROJECT, launch_finish(F, s));
   }
   LAUNCH(NMF_K_OTHER, launch_factor_out(Cf.t, (int)f, f_pad, K, KP, 0, C_out, s));

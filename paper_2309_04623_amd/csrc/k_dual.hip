@@ -41,7 +41,65 @@ __device__ __forceinline__ void load_tile(const float* p, f32x4 (&v)[4]) {
   for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(q + u);
 }
 
-template <int PREC, int KP, int MODE, int NW>
+// Operand registers of one 32-row tile: the L rows (A operand of Y = L Rt)
+// and the permuted L^T block (A operand of num/den).
+template <int PREC, int KP>
+struct Ops {
+  static constexpr int MT = KP / 32;
+  static constexpr int NL_F32 = (PREC == PREC_FP32) ? KP / 8 : 1;
+  static constexpr int NL_BF = (PREC == PREC_FP32) ? 1 : KP / 16;
+  static constexpr int NT_F32 = (PREC == PREC_FP32) ? MT * 4 : 1;
+  static constexpr int NT_BF = (PREC == PREC_FP32) ? 1 : MT * 2;
+  f32x4 lq[NL_F32];
+  bf16x8 lh[NL_BF], ll[NL_BF];
+  f32x4 tq[NT_F32];
+  bf16x8 th[NT_BF], tl[NT_BF];
+};
+
+template <int PREC, int KP>
+__device__ __forceinline__ void load_l(Ops<PREC, KP>& o, const DualArgs& a, int r0, int col,
+                                       int half) {
+  if constexpr (PREC == PREC_FP32) {
+    const f32x4* lp = reinterpret_cast<const f32x4*>(a.L + (int64_t)(r0 + col) * KP + half * (KP / 2));
+#pragma unroll
+    for (int u = 0; u < KP / 8; ++u) o.lq[u] = lp[u];
+  } else {
+    const bf16x8* lph = reinterpret_cast<const bf16x8*>(a.Lh + (int64_t)(r0 + col) * KP + 8 * half);
+    const bf16x8* lpl = reinterpret_cast<const bf16x8*>(a.Ll + (int64_t)(r0 + col) * KP + 8 * half);
+#pragma unroll
+    for (int j = 0; j < KP / 16; ++j) {
+      o.lh[j] = lph[2 * j];
+      o.ll[j] = lpl[2 * j];
+    }
+  }
+}
+
+template <int PREC, int KP>
+__device__ __forceinline__ void load_lt_tile(Ops<PREC, KP>& o, const DualArgs& a, int r0, int col,
+                                             int half, int t) {
+  if constexpr (PREC == PREC_FP32) {
+    const f32x4* lt = reinterpret_cast<const f32x4*>(a.LT + (int64_t)(32 * t + col) * a.ldlt + r0 + 16 * half);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) o.tq[4 * t + u] = lt[u];
+  } else {
+    const int64_t off = (int64_t)(32 * t + col) * a.ldlt + r0 + 8 * half;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      o.th[2 * t + j] = *reinterpret_cast<const bf16x8*>(a.LTh + off + 16 * j);
+      o.tl[2 * t + j] = *reinterpret_cast<const bf16x8*>(a.LTl + off + 16 * j);
+    }
+  }
+}
+
+template <int PREC, int KP>
+__device__ __forceinline__ void load_ops(Ops<PREC, KP>& o, const DualArgs& a, int r0, int col,
+                                         int half) {
+  load_l<PREC, KP>(o, a, r0, col, half);
+#pragma unroll
+  for (int t = 0; t < KP / 32; ++t) load_lt_tile<PREC, KP>(o, a, r0, col, half, t);
+}
+
+template <int PREC, int KP, int MODE, int NW, int PIPE>
 __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
   static_assert(KP % 32 == 0, "KP must be a multiple of 32");
   constexpr int MT = KP / 32;  // 32-row tiles of the num/den outputs
@@ -92,99 +150,48 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
   const int64_t tile_base = (int64_t)tc * a.RT;
   const float* dcol = a.D + tile_base * 1024 + lane * 16;
   const float* mcol = a.Mw + tile_base * 1024 + lane * 16;
-  // Operand registers of the current tile: the L rows (GEMM1 A operand) and
-  // the permuted L^T block (GEMM2 A operand).
-  constexpr bool PRELOAD = KP <= 64;
-  constexpr int NL_F32 = (PREC == PREC_FP32) ? KP / 8 : 1;
-  constexpr int NL_BF = (PREC == PREC_FP32) ? 1 : KP / 16;
-  constexpr int NT_F32 = (PREC == PREC_FP32) ? MT * 4 : 1;
-  constexpr int NT_BF = (PREC == PREC_FP32) ? 1 : MT * 2;
-  f32x4 lq[NL_F32];
-  bf16x8 lh[NL_BF], ll[NL_BF];
-  f32x4 tq[NT_F32];
-  bf16x8 th[NT_BF], tl[NT_BF];
+  // PIPE 0: operands loaded at their use (large KP); PIPE 1: all operands of
+  // a tile loaded at its start; PIPE 2: operands and data of the wave's next
+  // tile loaded one tile ahead, so every wait covers loads issued a full
+  // tile earlier.
+  using O = Ops<PREC, KP>;
+  const auto ops_for = [&](O& o, int r0) { load_ops<PREC, KP>(o, a, r0, col, half); };
 
-  // One tile: consume (dv, mv), prefetch the wave's next tile into (dn, mn).
-  auto step = [&](const int tr, const f32x4 (&dv)[4], const f32x4 (&mv)[4], f32x4 (&dn)[4],
-                  f32x4 (&mn)[4]) {
+  // One tile: consume (dv, mv, oc); prefetch the wave's next tile's data into
+  // (dn, mn) and, with PIPE 2, its operands into on.
+  auto step = [&](const int tr, const f32x4 (&dv)[4], const f32x4 (&mv)[4], O& oc, f32x4 (&dn)[4],
+                  f32x4 (&mn)[4], O& on) {
     const int r0 = tr * TILE;
-    // ---- 1. all operand loads of this tile (L2-resident factors) ----------
-    // With KP <= 64 every operand is loaded up front so that the waits for
-    // them leave the data prefetch in flight; larger KP would not fit the
-    // register file, so those operands are loaded at their use below.
-    if constexpr (PRELOAD) {
-      if constexpr (PREC == PREC_FP32) {
-        const f32x4* lp = reinterpret_cast<const f32x4*>(a.L + (int64_t)(r0 + col) * KP + half * (KP / 2));
-  #pragma unroll
-        for (int u = 0; u < KP / 8; ++u) lq[u] = lp[u];
-  #pragma unroll
-        for (int t = 0; t < MT; ++t) {
-          const f32x4* lt =
-              reinterpret_cast<const f32x4*>(a.LT + (int64_t)(32 * t + col) * a.ldlt + r0 + 16 * half);
-  #pragma unroll
-          for (int u = 0; u < 4; ++u) tq[4 * t + u] = lt[u];
-        }
-      } else {
-        const bf16x8* lph = reinterpret_cast<const bf16x8*>(a.Lh + (int64_t)(r0 + col) * KP + 8 * half);
-        const bf16x8* lpl = reinterpret_cast<const bf16x8*>(a.Ll + (int64_t)(r0 + col) * KP + 8 * half);
-  #pragma unroll
-        for (int j = 0; j < KP / 16; ++j) {
-          lh[j] = lph[2 * j];
-          ll[j] = lpl[2 * j];
-        }
-  #pragma unroll
-        for (int t = 0; t < MT; ++t) {
-          const int64_t off = (int64_t)(32 * t + col) * a.ldlt + r0 + 8 * half;
-  #pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            th[2 * t + j] = *reinterpret_cast<const bf16x8*>(a.LTh + off + 16 * j);
-            tl[2 * t + j] = *reinterpret_cast<const bf16x8*>(a.LTl + off + 16 * j);
-          }
-        }
-      }
+    // Unconditional (the last step re-reads its own tile) so that the number
+    // of loads in flight is static and the waits below stay precise.
+    const int trn = (tr + NW < t_end) ? tr + NW : tr;
+    if constexpr (PIPE == 2) {
+      ops_for(on, trn * TILE);
+    } else if constexpr (PIPE == 1) {
+      ops_for(oc, r0);
     }
     __builtin_amdgcn_sched_barrier(0);
-    // ---- 2. prefetch the next tile's data (stays in flight below) ---------
-    // Unconditional (the last step re-reads its own tile) so that the
-    // number of loads in flight is static and the operand waits below do
-    // not drain the prefetch.
-    const int trn = (tr + NW < t_end) ? tr + NW : tr;
     load_tile(dcol + (int64_t)trn * 1024, dn);
     load_tile(mcol + (int64_t)trn * 1024, mn);
     __builtin_amdgcn_sched_barrier(0);
 
-    // ---- 3. Y = L[r0:r0+32, :] * Rt ----------------------------------------
+    // ---- Y = L[r0:r0+32, :] * Rt ------------------------------------------
     f32x16 y = zero16();
-    if constexpr (!PRELOAD) {
-      if constexpr (PREC == PREC_FP32) {
-        const f32x4* lp =
-            reinterpret_cast<const f32x4*>(a.L + (int64_t)(r0 + col) * KP + half * (KP / 2));
-#pragma unroll
-        for (int u = 0; u < KP / 8; ++u) lq[u] = lp[u];
-      } else {
-        const bf16x8* lph = reinterpret_cast<const bf16x8*>(a.Lh + (int64_t)(r0 + col) * KP + 8 * half);
-        const bf16x8* lpl = reinterpret_cast<const bf16x8*>(a.Ll + (int64_t)(r0 + col) * KP + 8 * half);
-#pragma unroll
-        for (int j = 0; j < KP / 16; ++j) {
-          lh[j] = lph[2 * j];
-          ll[j] = lpl[2 * j];
-        }
-      }
-    }
+    if constexpr (PIPE == 0) load_l<PREC, KP>(oc, a, r0, col, half);
     if constexpr (PREC == PREC_FP32) {
 #pragma unroll
       for (int u = 0; u < KP / 8; ++u) {
-        y = mfma_f32(lq[u][0], rt[4 * u + 0], y);
-        y = mfma_f32(lq[u][1], rt[4 * u + 1], y);
-        y = mfma_f32(lq[u][2], rt[4 * u + 2], y);
-        y = mfma_f32(lq[u][3], rt[4 * u + 3], y);
+        y = mfma_f32(oc.lq[u][0], rt[4 * u + 0], y);
+        y = mfma_f32(oc.lq[u][1], rt[4 * u + 1], y);
+        y = mfma_f32(oc.lq[u][2], rt[4 * u + 2], y);
+        y = mfma_f32(oc.lq[u][3], rt[4 * u + 3], y);
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < KP / 16; ++j) y = mfma_bf16x3(lh[j], ll[j], rth[j], rtl[j], y);
+      for (int j = 0; j < KP / 16; ++j) y = mfma_bf16x3(oc.lh[j], oc.ll[j], rth[j], rtl[j], y);
     }
 
-    // ---- 4. elementwise: A = Mw o D, Z = Mw o Y, J += Mw (D - Y)^2 --------
+    // ---- elementwise: A = Mw o D, Z = Mw o Y, J += Mw (D - Y)^2 ------------
     float av[16], zv[16];
     float js = 0.f;
 #pragma unroll
@@ -200,21 +207,16 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
     }
     if constexpr (MODE != MODE_SPLIT) jacc += (double)js;
 
-    // ---- 5. num += L^T A, den += L^T Z -------------------------------------
+    // ---- num += L^T A, den += L^T Z ----------------------------------------
     if constexpr (MODE != MODE_OBJ) {
       if constexpr (PREC == PREC_FP32) {
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
-          if constexpr (!PRELOAD) {
-            const f32x4* lt =
-                reinterpret_cast<const f32x4*>(a.LT + (int64_t)(32 * t + col) * a.ldlt + r0 + 16 * half);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) tq[4 * t + u] = lt[u];
-          }
+          if constexpr (PIPE == 0) load_lt_tile<PREC, KP>(oc, a, r0, col, half, t);
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
-            num[t] = mfma_f32(tq[4 * t + (i >> 2)][i & 3], av[i], num[t]);
-            den[t] = mfma_f32(tq[4 * t + (i >> 2)][i & 3], zv[i], den[t]);
+            num[t] = mfma_f32(oc.tq[4 * t + (i >> 2)][i & 3], av[i], num[t]);
+            den[t] = mfma_f32(oc.tq[4 * t + (i >> 2)][i & 3], zv[i], den[t]);
           }
         }
       } else {
@@ -234,18 +236,11 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
         }
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
-          if constexpr (!PRELOAD) {
-            const int64_t off = (int64_t)(32 * t + col) * a.ldlt + r0 + 8 * half;
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-              th[2 * t + j] = *reinterpret_cast<const bf16x8*>(a.LTh + off + 16 * j);
-              tl[2 * t + j] = *reinterpret_cast<const bf16x8*>(a.LTl + off + 16 * j);
-            }
-          }
+          if constexpr (PIPE == 0) load_lt_tile<PREC, KP>(oc, a, r0, col, half, t);
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
-            num[t] = mfma_bf16x3(th[2 * t + j], tl[2 * t + j], ah[j], al[j], num[t]);
-            den[t] = mfma_bf16x3(th[2 * t + j], tl[2 * t + j], zh[j], zl[j], den[t]);
+            num[t] = mfma_bf16x3(oc.th[2 * t + j], oc.tl[2 * t + j], ah[j], al[j], num[t]);
+            den[t] = mfma_bf16x3(oc.th[2 * t + j], oc.tl[2 * t + j], zh[j], zl[j], den[t]);
           }
         }
       }
@@ -254,14 +249,16 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
 
   int tr = t_begin + wave;
   f32x4 dA[4], mA[4], dB[4], mB[4];
+  O oA, oB;
   if (tr < t_end) {
+    if constexpr (PIPE == 2) ops_for(oA, tr * TILE);
     load_tile(dcol + (int64_t)tr * 1024, dA);
     load_tile(mcol + (int64_t)tr * 1024, mA);
   }
   for (; tr < t_end; tr += 2 * NW) {
-    step(tr, dA, mA, dB, mB);
+    step(tr, dA, mA, oA, dB, mB, oB);
     if (tr + NW >= t_end) break;
-    step(tr + NW, dB, mB, dA, mA);
+    step(tr + NW, dB, mB, oB, dA, mA, oA);
   }
 
   // ---- combine the NW waves' sums in a fixed order -----------------------
@@ -348,42 +345,53 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
   }
 }
 
-template <int PREC, int KP, int MODE>
-static hipError_t launch_mode(int nw, const DualArgs& a, dim3 g, hipStream_t s) {
+template <int PREC, int KP, int MODE, int PIPE>
+static hipError_t launch_nw(int nw, const DualArgs& a, dim3 g, hipStream_t s) {
   switch (nw) {
-    case 1: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 1>), g, dim3(64), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 2>), g, dim3(128), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 4>), g, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 1, PIPE>), g, dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 2, PIPE>), g, dim3(128), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 4, PIPE>), g, dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+template <int PREC, int KP, int MODE>
+static hipError_t launch_mode(int nw, int pipe, const DualArgs& a, dim3 g, hipStream_t s) {
+  if constexpr (KP <= 64) {
+    if (pipe == 2) return launch_nw<PREC, KP, MODE, 2>(nw, a, g, s);
+    return launch_nw<PREC, KP, MODE, 1>(nw, a, g, s);
+  } else {
+    return launch_nw<PREC, KP, MODE, 0>(nw, a, g, s);
+  }
+}
+
 template <int PREC, int KP>
-static hipError_t launch_kp(int mode, int nw, const DualArgs& a, dim3 g, hipStream_t s) {
+static hipError_t launch_kp(int mode, int nw, int pipe, const DualArgs& a, dim3 g, hipStream_t s) {
   switch (mode) {
-    case MODE_UPDATE: return launch_mode<PREC, KP, MODE_UPDATE>(nw, a, g, s);
-    case MODE_SPLIT: return launch_mode<PREC, KP, MODE_SPLIT>(nw, a, g, s);
-    default: return launch_mode<PREC, KP, MODE_OBJ>(nw, a, g, s);
+    case MODE_UPDATE: return launch_mode<PREC, KP, MODE_UPDATE>(nw, pipe, a, g, s);
+    case MODE_SPLIT: return launch_mode<PREC, KP, MODE_SPLIT>(nw, pipe, a, g, s);
+    default: return launch_mode<PREC, KP, MODE_OBJ>(nw, pipe, a, g, s);
   }
 }
 
 template <int PREC>
-static hipError_t launch_prec(int kp, int mode, int nw, const DualArgs& a, dim3 g, hipStream_t s) {
+static hipError_t launch_prec(int kp, int mode, int nw, int pipe, const DualArgs& a, dim3 g,
+                              hipStream_t s) {
   switch (kp) {
-    case 32: return launch_kp<PREC, 32>(mode, nw, a, g, s);
-    case 64: return launch_kp<PREC, 64>(mode, nw, a, g, s);
-    case 96: return launch_kp<PREC, 96>(mode, nw, a, g, s);
-    case 128: return launch_kp<PREC, 128>(mode, nw, a, g, s);
+    case 32: return launch_kp<PREC, 32>(mode, nw, pipe, a, g, s);
+    case 64: return launch_kp<PREC, 64>(mode, nw, pipe, a, g, s);
+    case 96: return launch_kp<PREC, 96>(mode, nw, pipe, a, g, s);
+    case 128: return launch_kp<PREC, 128>(mode, nw, pipe, a, g, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_dual(int prec, int kp, int mode, int nw, const DualArgs& a, int grid_x,
+hipError_t launch_dual(int prec, int kp, int mode, int nw, int pipe, const DualArgs& a, int grid_x,
                        int grid_y, hipStream_t s) {
   const dim3 g(grid_x, grid_y);
-  if (prec == PREC_FP32) return launch_prec<PREC_FP32>(kp, mode, nw, a, g, s);
-  return launch_prec<PREC_BF16X3>(kp, mode, nw, a, g, s);
+  if (prec == PREC_FP32) return launch_prec<PREC_FP32>(kp, mode, nw, pipe, a, g, s);
+  return launch_prec<PREC_BF16X3>(kp, mode, nw, pipe, a, g, s);
 }
 
 }  // namespace nmf

@@ -54,8 +54,11 @@ struct DualArgs {
 
 enum DualMode { MODE_UPDATE = 0, MODE_SPLIT = 1, MODE_OBJ = 2 };
 
-// nw = waves per workgroup (1, 2 or 4); grid = (C_pad / 32, splits).
-hipError_t launch_dual(int prec, int kp, int mode, int nw, const DualArgs& a, int grid_x,
+// nw = waves per workgroup (1, 2 or 4); pipe = operand pipelining (2: the
+// next tile's operands and data one tile ahead, KP <= 64 only; otherwise the
+// current tile's operands at its start, or at their use for KP > 64);
+// grid = (C_pad / 32, splits).
+hipError_t launch_dual(int prec, int kp, int mode, int nw, int pipe, const DualArgs& a, int grid_x,
                        int grid_y, hipStream_t s);
 
 // Finishes a split half-step: sums the partials in a fixed order, applies

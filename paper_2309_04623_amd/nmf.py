@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
         ("struct_size", ctypes.c_uint32), ("k", ctypes.c_int32), ("max_iter", ctypes.c_int32),
         ("check_every", ctypes.c_int32), ("tol", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("precision", ctypes.c_int32), ("flags", ctypes.c_int32), ("floor_eps", ctypes.c_float),
-        ("split", ctypes.c_int32), ("waves", ctypes.c_int32),
+        ("split", ctypes.c_int32), ("waves", ctypes.c_int32), ("pipeline", ctypes.c_int32),
     ]
 
 
@@ -171,7 +171,7 @@ def default_handle(device: int = 0) -> Handle:
 
 
 def make_params(k, iters, precision="fp32", seed=0, flags=0, eps=1e-30, split=0, tol=0.0,
-                check_every=0, waves=0) -> Params:
+                check_every=0, waves=0, pipeline=0) -> Params:
     p = Params()
     lib().nmf_params_default(ctypes.byref(p))
     p.k = int(k)
@@ -184,6 +184,7 @@ def make_params(k, iters, precision="fp32", seed=0, flags=0, eps=1e-30, split=0,
     p.tol = float(tol)
     p.check_every = int(check_every)
     p.waves = int(waves)
+    p.pipeline = int(pipeline)
     return p
 
 
@@ -219,7 +220,7 @@ def objective(V, M, W, H, precision="fp32", handle=None) -> float:
 
 
 def build_basis(V, M, k, iters, *, precision="fp32", W_init=None, H_init=None, seed=0, flags=0,
-                eps=1e-30, split=0, tol=0.0, check_every=0, waves=0, handle=None):
+                eps=1e-30, split=0, tol=0.0, check_every=0, waves=0, pipeline=0, handle=None):
     """Basis construction (Eq. 3 iterated).  Returns (W, H, J history, report)."""
     torch = _torch()
     dev = V.device.index or 0
@@ -229,7 +230,8 @@ def build_basis(V, M, k, iters, *, precision="fp32", W_init=None, H_init=None, s
     W = torch.empty((n, k), dtype=f32, device=V.device)
     H = torch.empty((k, p), dtype=f32, device=V.device)
     hist = np.zeros(iters + 1, np.float64)
-    prm = make_params(k, iters, precision, seed, flags, eps, split, tol, check_every, waves)
+    prm = make_params(k, iters, precision, seed, flags, eps, split, tol, check_every, waves,
+                      pipeline)
     rep = _new_report()
     st = _check(lib().nmf_build_basis(
         h.h, _dev_ptr(V, "V", f32), _dev_ptr(M, "M", f32), n, p, ctypes.byref(prm),
