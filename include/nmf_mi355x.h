@@ -206,6 +206,50 @@ int nmf_subtract(nmf_handle h, const float* H, const float* C, const float* T,
                  const float* M_T, int64_t f, int64_t k, int64_t p, const float* scale,
                  float* model_out, float* resid_out, void* stream);
 
+/* ---- learned warm start of the projection ---------------------------------
+ * Not part of the paper's method: a small network predicts each frame's
+ * coefficients so that the Eq. 3 W-rule iteration (target modelling,
+ * Sec. 4.1) starts near its limit; cold start stays the fallback.
+ *   x = masked-mean-pool(t) / s  (32 x 32 grid over the frame padded with
+ *       weight 0 to a multiple of 32 per axis; s = masked mean of t)
+ *   a1 = x W1 + b1, h1 = gelu(a1)    1024 -> 512
+ *   a2 = h1 W2 + b2, h2 = gelu(a2)   512 -> 512
+ *   z = h2 W3 + b3                   512 -> k
+ *   c = max(s softplus(z), 1e-6 s)
+ * The model state is one device float array: parameters in the order
+ * W1 (1024 x 512), b1 (512), W2 (512 x 512), b2 (512), W3 (512 x k), b3 (k),
+ * row-major, followed by the two Adam moment arrays of the same length.
+ * GEMMs run on bf16 MFMA with FP32 accumulation; precision NMF_PREC_FP32
+ * selects the split (bf16x3) products, NMF_PREC_BF16X3 is accepted as the
+ * same, any other value rounds operands to bf16 (use 2).                   */
+#define NMF_WS_IN 1024
+#define NMF_WS_HIDDEN 512
+#define NMF_PREC_BF16 2
+/* Parameter count of the network for k outputs (the state holds 3x this). */
+int64_t nmf_warmstart_param_count(int32_t k);
+/* He-normal weights, zero biases and moments from the seeded generator. */
+int nmf_warmstart_init(nmf_handle h, float* state, int32_t k, uint64_t seed, void* stream);
+/* Pool f dense frames (f x ny*nx) into X_out (f x 1024) and s_out (f). */
+int nmf_warmstart_pool(nmf_handle h, const float* T, const float* M_T, int64_t f, int32_t ny,
+                       int32_t nx, float* X_out, float* s_out, void* stream);
+/* One step on a batch of b rows: forward, loss
+ *   L = mean_f (c_f - c*_f) G (c_f - c*_f)^T / (c*_f G c*_f^T),  G = H H^T,
+ * backward, and an Adam update (lr > 0; step_index counts from 1).
+ * grads_out: nullable parameter-sized gradient; loss_out: [host].        */
+int nmf_warmstart_step(nmf_handle h, float* state, const float* X, const float* s,
+                       const float* c_star, const float* G, int32_t b, int32_t k,
+                       int32_t precision, float lr, int32_t step_index, float* grads_out,
+                       double* loss_out, void* stream);
+/* Epochs of shuffled minibatches over m rows (X: m x 1024, s: m, c_star:
+ * m x k).  loss_hist: [host] nullable, one mean training loss per epoch.  */
+int nmf_warmstart_train(nmf_handle h, float* state, const float* X, const float* s,
+                        const float* c_star, const float* G, int64_t m, int32_t k,
+                        int32_t precision, int32_t epochs, int32_t batch, float lr,
+                        uint64_t seed, double* loss_hist, void* stream);
+/* Predicted coefficients C_out (f x k) for pooled frames X, s. */
+int nmf_warmstart_infer(nmf_handle h, const float* state, const float* X, const float* s,
+                        int64_t f, int32_t k, int32_t precision, float* C_out, void* stream);
+
 /* ---- live kernel timing ----------------------------------------------------
  * Opt-in instrumentation for measurement: while enabled, every kernel the
  * handle launches is bracketed by two HIP events recorded on the call's

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/nmf_mi355x.h"
+#include "device_common.hpp"
 #include "kernels.hpp"
 
 using namespace nmf;
@@ -1051,6 +1052,279 @@ int nmf_profile_get(nmf_handle h, int32_t kernel_class, int64_t* count, double* 
   HIP_TRY(prof_drain(h));
   *count = h->prof_n[kernel_class];
   *total_ms = h->prof_ms[kernel_class];
+  return NMF_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Learned warm start
+// ===========================================================================
+namespace {
+
+constexpr int WS_IN = NMF_WS_IN, WS_H = NMF_WS_HIDDEN;
+constexpr float WS_FLOOR = 1e-6f;
+
+struct WsLayout {
+  int64_t W1, b1, W2, b2, W3, b3, count;
+  explicit WsLayout(int k) {
+    W1 = 0;
+    b1 = W1 + (int64_t)WS_IN * WS_H;
+    W2 = b1 + WS_H;
+    b2 = W2 + (int64_t)WS_H * WS_H;
+    W3 = b2 + WS_H;
+    b3 = W3 + (int64_t)WS_H * k;
+    count = b3 + k;
+  }
+};
+
+LinearArgs lin(const float* A, int64_t sa0, int64_t sa1, const float* B, int64_t sb0, int64_t sb1,
+               const float* bias, float* C, float* Hact, int64_t ldc, int M, int N, int Kd, int act,
+               int x3) {
+  LinearArgs a{};
+  a.A = A;
+  a.sa0 = sa0;
+  a.sa1 = sa1;
+  a.B = B;
+  a.sb0 = sb0;
+  a.sb1 = sb1;
+  a.bias = bias;
+  a.C = C;
+  a.Hact = Hact;
+  a.ldc = ldc;
+  a.M = M;
+  a.N = N;
+  a.Kd = Kd;
+  a.act = act;
+  a.x3 = x3;
+  return a;
+}
+
+struct WsBufs {
+  float *A1, *H1, *A2, *H2, *Z, *W, *D, *U, *V, *dW, *dZ, *dH, *dA, *grads, *Xb, *sb, *cb;
+  double* lrow;
+  int* idx;
+};
+
+int ws_bufs(nmf_handle h, int b, int k, int64_t nparam, WsBufs* o) {
+  int rc;
+  const size_t bh = (size_t)b * WS_H, bk = (size_t)b * k;
+  if ((rc = ws(h, "ws.A1", bh, &o->A1)) || (rc = ws(h, "ws.H1", bh, &o->H1)) ||
+      (rc = ws(h, "ws.A2", bh, &o->A2)) || (rc = ws(h, "ws.H2", bh, &o->H2)) ||
+      (rc = ws(h, "ws.Z", bk, &o->Z)) || (rc = ws(h, "ws.W", bk, &o->W)) ||
+      (rc = ws(h, "ws.D", bk, &o->D)) || (rc = ws(h, "ws.U", bk, &o->U)) ||
+      (rc = ws(h, "ws.V", bk, &o->V)) ||
+      (rc = ws(h, "ws.dW", bk, &o->dW)) || (rc = ws(h, "ws.dZ", bk, &o->dZ)) ||
+      (rc = ws(h, "ws.dH", bh, &o->dH)) || (rc = ws(h, "ws.dA", bh, &o->dA)) ||
+      (rc = ws(h, "ws.grads", (size_t)nparam, &o->grads)) ||
+      (rc = ws(h, "ws.lrow", (size_t)b, &o->lrow)) || (rc = ws(h, "ws.Xb", (size_t)b * WS_IN, &o->Xb)) ||
+      (rc = ws(h, "ws.sb", (size_t)b, &o->sb)) || (rc = ws(h, "ws.cb", bk, &o->cb)) ||
+      (rc = ws(h, "ws.idx", (size_t)b, &o->idx)))
+    return rc;
+  return NMF_OK;
+}
+
+int x3_of(int precision) { return precision == NMF_PREC_BF16 ? 0 : 1; }
+
+// Forward pass for b rows: activations into the buffers, predictions into W.
+hipError_t ws_forward(nmf_handle h, const float* P, const WsLayout& L, const float* X, const float* s,
+                      int b, int k, int x3, const WsBufs& B, float* Wout, hipStream_t st) {
+  hipError_t e;
+  LinearArgs l1 = lin(X, WS_IN, 1, P + L.W1, WS_H, 1, P + L.b1, B.A1, B.H1, WS_H, b, WS_H, WS_IN,
+                      ACT_GELU, x3);
+  if ((e = timed(h, NMF_K_OTHER, st, [&]() { return launch_linear(l1, st); }))) return e;
+  LinearArgs l2 = lin(B.H1, WS_H, 1, P + L.W2, WS_H, 1, P + L.b2, B.A2, B.H2, WS_H, b, WS_H, WS_H,
+                      ACT_GELU, x3);
+  if ((e = timed(h, NMF_K_OTHER, st, [&]() { return launch_linear(l2, st); }))) return e;
+  LinearArgs l3 = lin(B.H2, WS_H, 1, P + L.W3, k, 1, P + L.b3, B.Z, nullptr, k, b, k, WS_H,
+                      ACT_NONE, x3);
+  if ((e = timed(h, NMF_K_OTHER, st, [&]() { return launch_linear(l3, st); }))) return e;
+  return timed(h, NMF_K_OTHER, st, [&]() { return launch_head(B.Z, s, b, k, WS_FLOOR, Wout, st); });
+}
+
+// Loss + backward for b rows (after ws_forward into B.W); gradients into
+// B.grads in the parameter layout; per-row loss terms into B.lrow.
+hipError_t ws_backward(nmf_handle h, const float* P, const WsLayout& L, const float* X,
+                       const float* s, const float* cstar, const float* G, int b, int k, int x3,
+                       const WsBufs& B, hipStream_t st) {
+  hipError_t e;
+  auto T = [&](auto fn) { return timed(h, NMF_K_OTHER, st, fn); };
+  float* g = B.grads;
+  // U = (w - c*) G and V = c* G, always with split products (small GEMMs)
+  if ((e = T([&]() { return launch_sub(B.W, cstar, (int64_t)b * k, B.D, st); }))) return e;
+  LinearArgs lu = lin(B.D, k, 1, G, k, 1, nullptr, B.U, nullptr, k, b, k, k, ACT_NONE, 1);
+  if ((e = T([&]() { return launch_linear(lu, st); }))) return e;
+  LinearArgs lv = lin(cstar, k, 1, G, k, 1, nullptr, B.V, nullptr, k, b, k, k, ACT_NONE, 1);
+  if ((e = T([&]() { return launch_linear(lv, st); }))) return e;
+  if ((e = T([&]() { return launch_loss(B.W, cstar, B.U, B.V, b, k, B.dW, B.lrow, st); }))) return e;
+  // head
+  if ((e = T([&]() { return launch_head_bwd(B.dW, B.Z, s, b, k, B.dZ, st); }))) return e;
+  LinearArgs g3 = lin(B.H2, 1, WS_H, B.dZ, k, 1, nullptr, g + L.W3, nullptr, k, WS_H, k, b, ACT_NONE, x3);
+  if ((e = T([&]() { return launch_linear(g3, st); }))) return e;
+  if ((e = T([&]() { return launch_colsum(B.dZ, b, k, g + L.b3, st); }))) return e;
+  // layer 2
+  LinearArgs d2 = lin(B.dZ, k, 1, P + L.W3, 1, k, nullptr, B.dH, nullptr, WS_H, b, WS_H, k, ACT_NONE, x3);
+  if ((e = T([&]() { return launch_linear(d2, st); }))) return e;
+  if ((e = T([&]() { return launch_gelu_bwd(B.dH, B.A2, (int64_t)b * WS_H, B.dA, st); }))) return e;
+  LinearArgs g2 = lin(B.H1, 1, WS_H, B.dA, WS_H, 1, nullptr, g + L.W2, nullptr, WS_H, WS_H, WS_H, b,
+                      ACT_NONE, x3);
+  if ((e = T([&]() { return launch_linear(g2, st); }))) return e;
+  if ((e = T([&]() { return launch_colsum(B.dA, b, WS_H, g + L.b2, st); }))) return e;
+  // layer 1
+  LinearArgs d1 = lin(B.dA, WS_H, 1, P + L.W2, 1, WS_H, nullptr, B.dH, nullptr, WS_H, b, WS_H, WS_H,
+                      ACT_NONE, x3);
+  if ((e = T([&]() { return launch_linear(d1, st); }))) return e;
+  if ((e = T([&]() { return launch_gelu_bwd(B.dH, B.A1, (int64_t)b * WS_H, B.dA, st); }))) return e;
+  LinearArgs g1 = lin(X, 1, WS_IN, B.dA, WS_H, 1, nullptr, g + L.W1, nullptr, WS_H, WS_IN, WS_H, b,
+                      ACT_NONE, x3);
+  if ((e = T([&]() { return launch_linear(g1, st); }))) return e;
+  return T([&]() { return launch_colsum(B.dA, b, WS_H, g + L.b1, st); });
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t nmf_warmstart_param_count(int32_t k) { return k > 0 ? WsLayout(k).count : 0; }
+
+int nmf_warmstart_init(nmf_handle h, float* state, int32_t k, uint64_t seed, void* stream) {
+  if (!state) return fail(NMF_ERR_ARG, "state is NULL");
+  if (k < 1 || k > 4096) return fail(NMF_ERR_ARG, "k must be in [1, 4096]");
+  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+  DeviceGuard g(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const WsLayout L(k);
+  HIP_TRY(hipMemsetAsync(state, 0, sizeof(float) * 3 * L.count, s));
+  LAUNCH(NMF_K_OTHER, launch_normal_init(state + L.W1, L.b1 - L.W1, std::sqrt(2.f / WS_IN), seed, 10, s));
+  LAUNCH(NMF_K_OTHER, launch_normal_init(state + L.W2, L.b2 - L.W2, std::sqrt(2.f / WS_H), seed, 11, s));
+  LAUNCH(NMF_K_OTHER, launch_normal_init(state + L.W3, L.b3 - L.W3, std::sqrt(1.f / WS_H), seed, 12, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(prof_drain(h));
+  return NMF_OK;
+}
+
+int nmf_warmstart_pool(nmf_handle h, const float* T, const float* M_T, int64_t f, int32_t ny,
+                       int32_t nx, float* X_out, float* s_out, void* stream) {
+  if (!T || !M_T || !X_out || !s_out) return fail(NMF_ERR_ARG, "NULL array argument");
+  if (f < 1 || f > 0x7fffffff || ny < 1 || nx < 1) return fail(NMF_ERR_SHAPE, "bad frame shape");
+  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+  DeviceGuard g(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  LAUNCH(NMF_K_OTHER, launch_pool(T, M_T, (int)f, ny, nx, X_out, s_out, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(prof_drain(h));
+  return NMF_OK;
+}
+
+int nmf_warmstart_infer(nmf_handle h, const float* state, const float* X, const float* s_in,
+                        int64_t f, int32_t k, int32_t precision, float* C_out, void* stream) {
+  if (!state || !X || !s_in || !C_out) return fail(NMF_ERR_ARG, "NULL array argument");
+  if (f < 1 || f > 0x7fffffff) return fail(NMF_ERR_SHAPE, "bad row count");
+  if (k < 1 || k > 4096) return fail(NMF_ERR_ARG, "k must be in [1, 4096]");
+  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+  DeviceGuard g(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const WsLayout L(k);
+  const int x3 = x3_of(precision);
+  const int chunk = 4096;
+  WsBufs B;
+  int rc;
+  if ((rc = ws_bufs(h, (int)std::min<int64_t>(f, chunk), k, L.count, &B))) return rc;
+  for (int64_t r0 = 0; r0 < f; r0 += chunk) {
+    const int b = (int)std::min<int64_t>(chunk, f - r0);
+    HIP_TRY(ws_forward(h, state, L, X + r0 * WS_IN, s_in + r0, b, k, x3, B, C_out + r0 * k, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(prof_drain(h));
+  return NMF_OK;
+}
+
+int nmf_warmstart_step(nmf_handle h, float* state, const float* X, const float* s_in,
+                       const float* c_star, const float* G, int32_t b, int32_t k,
+                       int32_t precision, float lr, int32_t step_index, float* grads_out,
+                       double* loss_out, void* stream) {
+  if (!state || !X || !s_in || !c_star || !G) return fail(NMF_ERR_ARG, "NULL array argument");
+  if (b < 1 || b > 65535) return fail(NMF_ERR_SHAPE, "batch must be in [1, 65535]");
+  if (k < 1 || k > 4096) return fail(NMF_ERR_ARG, "k must be in [1, 4096]");
+  if (lr > 0.f && step_index < 1) return fail(NMF_ERR_ARG, "step_index counts from 1");
+  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+  DeviceGuard g(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const WsLayout L(k);
+  const int x3 = x3_of(precision);
+  WsBufs B;
+  int rc;
+  if ((rc = ws_bufs(h, b, k, L.count, &B))) return rc;
+  HIP_TRY(ws_forward(h, state, L, X, s_in, b, k, x3, B, B.W, s));
+  HIP_TRY(ws_backward(h, state, L, X, s_in, c_star, G, b, k, x3, B, s));
+  if (grads_out)
+    HIP_TRY(hipMemcpyAsync(grads_out, B.grads, sizeof(float) * L.count, hipMemcpyDeviceToDevice, s));
+  if (lr > 0.f)
+    LAUNCH(NMF_K_OTHER, launch_adam(state, B.grads, state + L.count, state + 2 * L.count, L.count,
+                                    lr, 0.9f, 0.999f, 1e-8f, step_index, s));
+  std::vector<double> lrow(b);
+  HIP_TRY(hipMemcpyAsync(lrow.data(), B.lrow, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(prof_drain(h));
+  double sum = 0.0;
+  for (double v : lrow) sum += v;
+  if (loss_out) *loss_out = sum / b;
+  if (!std::isfinite(sum)) return fail(NMF_ERR_DIVERGED, "warm-start loss became non-finite");
+  return NMF_OK;
+}
+
+int nmf_warmstart_train(nmf_handle h, float* state, const float* X, const float* s_in,
+                        const float* c_star, const float* G, int64_t m, int32_t k,
+                        int32_t precision, int32_t epochs, int32_t batch, float lr,
+                        uint64_t seed, double* loss_hist, void* stream) {
+  if (!state || !X || !s_in || !c_star || !G) return fail(NMF_ERR_ARG, "NULL array argument");
+  if (m < 1 || m > 0x7fffffff) return fail(NMF_ERR_SHAPE, "bad row count");
+  if (batch < 1 || batch > 65535) return fail(NMF_ERR_SHAPE, "batch must be in [1, 65535]");
+  if (epochs < 0 || !(lr > 0.f)) return fail(NMF_ERR_ARG, "epochs >= 0 and lr > 0 required");
+  if (k < 1 || k > 4096) return fail(NMF_ERR_ARG, "k must be in [1, 4096]");
+  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+  DeviceGuard g(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const WsLayout L(k);
+  const int x3 = x3_of(precision);
+  const int b = (int)std::min<int64_t>(batch, m);
+  WsBufs B;
+  int rc;
+  if ((rc = ws_bufs(h, b, k, L.count, &B))) return rc;
+  std::vector<int> perm(m);
+  int step = 0;
+  for (int ep = 0; ep < epochs; ++ep) {
+    // Fisher-Yates shuffle driven by the counter-based generator
+    for (int64_t i = 0; i < m; ++i) perm[i] = (int)i;
+    const uint64_t key = sm_key(seed, 100 + ep);
+    for (int64_t i = m - 1; i > 0; --i) {
+      const uint64_t u = sm_mix(key + (uint64_t)(i + 1) * SM_GAMMA);
+      const int64_t j = (int64_t)(u % (uint64_t)(i + 1));
+      std::swap(perm[i], perm[j]);
+    }
+    double ep_loss = 0.0;
+    int64_t nb = 0;
+    std::vector<double> lrow(b);
+    for (int64_t r0 = 0; r0 + b <= m; r0 += b) {
+      HIP_TRY(hipMemcpyAsync(B.idx, perm.data() + r0, sizeof(int) * b, hipMemcpyHostToDevice, s));
+      LAUNCH(NMF_K_OTHER, launch_gather(X, B.idx, b, WS_IN, B.Xb, s));
+      LAUNCH(NMF_K_OTHER, launch_gather(s_in, B.idx, b, 1, B.sb, s));
+      LAUNCH(NMF_K_OTHER, launch_gather(c_star, B.idx, b, k, B.cb, s));
+      ++step;
+      HIP_TRY(ws_forward(h, state, L, B.Xb, B.sb, b, k, x3, B, B.W, s));
+      HIP_TRY(ws_backward(h, state, L, B.Xb, B.sb, B.cb, G, b, k, x3, B, s));
+      LAUNCH(NMF_K_OTHER, launch_adam(state, B.grads, state + L.count, state + 2 * L.count,
+                                      L.count, lr, 0.9f, 0.999f, 1e-8f, step, s));
+      HIP_TRY(hipMemcpyAsync(lrow.data(), B.lrow, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      for (double v : lrow) ep_loss += v;
+      nb += b;
+    }
+    if (loss_hist) loss_hist[ep] = nb ? ep_loss / nb : 0.0;
+    if (!std::isfinite(ep_loss)) return fail(NMF_ERR_DIVERGED, "warm-start loss became non-finite");
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(prof_drain(h));
   return NMF_OK;
 }
 

@@ -14,6 +14,8 @@
 // Pixels appear only through the staged chunks, so dense frames (all
 // pixels, weight row of M_T) and CSR frames share the kernel.
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -34,14 +36,22 @@ __device__ __forceinline__ void tile_of(int idx, int nb, int& mi, int& mj) {
   mj = mi + idx;
 }
 
+template <int KP>
+__host__ __device__ constexpr int gram_waves() {
+  return KP <= 128 ? 4 : 8;
+}
+
 template <int KP, bool RAGGED>
-__global__ __launch_bounds__(256) void k_gram(GramArgs a) {
+__global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   extern __shared__ __align__(16) float lds[];
   __shared__ int qslot;
   constexpr int NB = KP / 32;
   constexpr int NT = gram_tiles<KP>();
-  constexpr int TPW = (NT + 3) / 4;
+  constexpr int NWV = gram_waves<KP>();
+  constexpr int NTH = 64 * NWV;
+  constexpr int TPW = (NT + NWV - 1) / NWV;
   constexpr int KQ = KP / 4;
+  constexpr int FOLD = 8;  // chunks summed in FP32 before folding into FP64
   const int K = a.K;
   float* Hs = lds;            // [32][KP] gathered H^T rows
   float* ms = lds + 32 * KP;  // [32] weights
@@ -56,7 +66,7 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs a) {
   int tmi[TPW], tmj[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
-    const int idx = wave + 4 * q;
+    const int idx = wave + NWV * q;
     if (idx < NT) {
       tile_of(idx, NB, tmi[q], tmj[q]);
     } else {
@@ -88,14 +98,31 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs a) {
       }
     }
 
+    // Totals: FP64 when they fit the register file (KP <= 160), else FP32.
+    constexpr bool TOT64 = KP <= 160;
+    using tot_t = typename std::conditional<TOT64, double, float>::type;
     f32x16 acc[TPW];
+    tot_t tot[TPW][16];
 #pragma unroll
-    for (int q = 0; q < TPW; ++q) acc[q] = zero16();
+    for (int q = 0; q < TPW; ++q) {
+      acc[q] = zero16();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) tot[q][r] = 0;
+    }
+    auto fold = [&]() {
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) tot[q][r] += (tot_t)acc[q][r];
+        acc[q] = zero16();
+      }
+    };
     double bacc = 0.0;
+    int nfold = 0;
 
     for (int64_t base = s; base < e; base += 32) {
       // ---- stage 32 pixels: rows of H^T, weights, data -------------------
-      for (int x = tid; x < 32 * KQ; x += 256) {
+      for (int x = tid; x < 32 * KQ; x += NTH) {
         const int jr = x / KQ, kq = x - jr * KQ;
         const int64_t jj = base + jr;
         f32x4 v = {0.f, 0.f, 0.f, 0.f};
@@ -170,8 +197,15 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs a) {
 #pragma unroll 8
         for (int jr = 0; jr < 32; ++jr) bacc += (double)(Hs[jr * KP + tid] * ms[jr]) * (double)ts[jr];
       }
+      // Two-level sum: FOLD chunks in the FP32 MFMA accumulators, then into
+      // FP64 totals (G entries are sums of up to P_f / 2 positive terms).
+      if (++nfold == FOLD) {
+        nfold = 0;
+        fold();
+      }
       __syncthreads();
     }
+    fold();
 
     // ---- G to LDS (both triangles), b and the starting coefficients -------
 #pragma unroll
@@ -182,8 +216,9 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs a) {
           const int row = 32 * tmi[q] + acc_row(r, half);
           const int cg = 32 * tmj[q] + col;
           if (row < K && cg < K) {
-            G[row * K + cg] = acc[q][r];
-            if (tmi[q] != tmj[q]) G[cg * K + row] = acc[q][r];
+            const float v = (float)tot[q][r];
+            G[row * K + cg] = v;
+            if (tmi[q] != tmj[q]) G[cg * K + row] = v;
           }
         }
       }
@@ -255,7 +290,7 @@ static hipError_t gram_launch(const GramArgs& a, int max_blocks, hipStream_t s, 
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * gram_waves<KP>(), lds);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   int dev = 0, cus = 0;
@@ -264,7 +299,7 @@ static hipError_t gram_launch(const GramArgs& a, int max_blocks, hipStream_t s, 
   int grid = std::max(1, std::min(a.F, cus * per_cu));
   if (max_blocks > 0) grid = std::min(grid, max_blocks);
   if (grid_out) *grid_out = grid;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(64 * gram_waves<KP>()), lds, s, a);
   return hipGetLastError();
 }
 

@@ -182,4 +182,38 @@ hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, h
 constexpr int MAX_SORT_FRAMES = 8192;
 hipError_t launch_frame_order(const int64_t* offsets, int f, int* order, hipStream_t s);
 
+// ---- learned warm start ---------------------------------------------------
+enum { ACT_NONE = 0, ACT_GELU = 1 };
+struct LinearArgs {
+  const float* A;  // A(i, k) = A[i * sa0 + k * sa1]
+  int64_t sa0, sa1;
+  const float* B;  // B(k, j) = B[k * sb0 + j * sb1]
+  int64_t sb0, sb1;
+  const float* bias;  // nullable, N
+  float* C;           // M x N, row stride ldc (pre-activation)
+  float* Hact;        // act(C) when act != ACT_NONE
+  int64_t ldc;
+  int M, N, Kd;
+  int act;
+  int x3;  // 1: split-precision bf16x3 products, 0: bf16 operands
+};
+hipError_t launch_linear(const LinearArgs& a, hipStream_t s);
+hipError_t launch_head(const float* z, const float* s, int B, int K, float floor_rel, float* w,
+                       hipStream_t st);
+hipError_t launch_head_bwd(const float* dw, const float* z, const float* s, int B, int K,
+                           float* dz, hipStream_t st);
+hipError_t launch_gelu_bwd(const float* dh, const float* a, int64_t n, float* da, hipStream_t st);
+hipError_t launch_loss(const float* w, const float* cstar, const float* U, const float* V, int B,
+                       int K, float* dw, double* lrow, hipStream_t st);
+hipError_t launch_sub(const float* a, const float* b, int64_t n, float* out, hipStream_t st);
+hipError_t launch_colsum(const float* d, int B, int N, float* out, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, int t, hipStream_t st);
+hipError_t launch_gather(const float* src, const int* idx, int rows, int n, float* out,
+                         hipStream_t st);
+hipError_t launch_pool(const float* T, const float* MT, int f, int ny, int nx, float* X, float* s,
+                       hipStream_t st);
+hipError_t launch_normal_init(float* p, int64_t n, float std, uint64_t seed, int stream_id,
+                              hipStream_t st);
+
 }  // namespace nmf

@@ -74,6 +74,14 @@ _SIGS = {
                                           ctypes.POINTER(Report), _vp]),
     "nmf_device_clock_khz": (ctypes.c_double, [_vp]),
     "nmf_subtract": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp]),
+    "nmf_warmstart_param_count": (ctypes.c_int64, [_i32]),
+    "nmf_warmstart_init": (ctypes.c_int, [_vp, _vp, _i32, _u64, _vp]),
+    "nmf_warmstart_pool": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp]),
+    "nmf_warmstart_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32,
+                                          ctypes.c_float, _i32, _vp, _dp, _vp]),
+    "nmf_warmstart_train": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32,
+                                           _i32, ctypes.c_float, _u64, _dp, _vp]),
+    "nmf_warmstart_infer": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]),
     "nmf_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "nmf_profile_get": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double)]),
@@ -320,3 +328,103 @@ def project_ragged(H, offsets, pix, val, wt, iters, *, C_init=None, seed=0, flag
 def device_clock_khz(handle=None, device=0) -> float:
     h = handle or default_handle(device)
     return float(lib().nmf_device_clock_khz(h.h))
+
+
+# ---------------------------------------------------------------------------
+# learned warm start
+# ---------------------------------------------------------------------------
+WS_IN, WS_HIDDEN = 1024, 512
+WS_PREC = {"fp32": 0, "bf16x3": 1, "bf16": 2}
+WS_NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def ws_shapes(k):
+    return [(WS_IN, WS_HIDDEN), (WS_HIDDEN,), (WS_HIDDEN, WS_HIDDEN), (WS_HIDDEN,), (WS_HIDDEN, k), (k,)]
+
+
+def ws_param_count(k):
+    return int(lib().nmf_warmstart_param_count(k))
+
+
+def ws_state_from_params(params, k, device="cuda:0"):
+    """Pack host parameters (dict of arrays) into a device state with zero
+    Adam moments."""
+    torch = _torch()
+    flat = np.concatenate([np.asarray(params[n], np.float64).reshape(-1) for n in WS_NAMES])
+    assert flat.size == ws_param_count(k)
+    st = np.zeros(3 * flat.size, np.float32)
+    st[: flat.size] = flat
+    return torch.from_numpy(st).to(device)
+
+
+def ws_unpack(vec, k):
+    """Split a parameter-sized vector (state prefix or gradients) by name."""
+    v = vec.detach().cpu().numpy().astype(np.float64) if hasattr(vec, "detach") else np.asarray(vec)
+    out, o = {}, 0
+    for n, shp in zip(WS_NAMES, ws_shapes(k)):
+        c = int(np.prod(shp))
+        out[n] = v[o:o + c].reshape(shp)
+        o += c
+    return out
+
+
+def ws_init(k, seed=0, handle=None, device=0):
+    torch = _torch()
+    h = handle or default_handle(device)
+    st = torch.empty(3 * ws_param_count(k), dtype=torch.float32, device=f"cuda:{device}")
+    _check(lib().nmf_warmstart_init(h.h, st.data_ptr(), k, seed, _stream(device)))
+    return st
+
+
+def ws_pool(T, MT, ny, nx, handle=None):
+    torch = _torch()
+    dev = T.device.index or 0
+    h = handle or default_handle(dev)
+    f = T.shape[0]
+    X = torch.empty((f, WS_IN), dtype=torch.float32, device=T.device)
+    s = torch.empty(f, dtype=torch.float32, device=T.device)
+    _check(lib().nmf_warmstart_pool(h.h, _dev_ptr(T, "T", torch.float32), _dev_ptr(MT, "M_T", torch.float32),
+                                    f, ny, nx, X.data_ptr(), s.data_ptr(), _stream(dev)))
+    return X, s
+
+
+def ws_step(state, X, s, cstar, G, k, precision="fp32", lr=0.0, step=1, want_grads=False,
+            handle=None):
+    torch = _torch()
+    dev = state.device.index or 0
+    h = handle or default_handle(dev)
+    b = X.shape[0]
+    grads = torch.empty(ws_param_count(k), dtype=torch.float32, device=state.device) if want_grads else None
+    loss = ctypes.c_double()
+    f32 = torch.float32
+    _check(lib().nmf_warmstart_step(h.h, _dev_ptr(state, "state", f32), _dev_ptr(X, "X", f32),
+                                    _dev_ptr(s, "s", f32), _dev_ptr(cstar, "c_star", f32),
+                                    _dev_ptr(G, "G", f32), b, k, WS_PREC[precision], lr, step,
+                                    _dev_ptr(grads, "grads"), ctypes.addressof(loss), _stream(dev)))
+    return (loss.value, grads) if want_grads else loss.value
+
+
+def ws_train(state, X, s, cstar, G, k, epochs, batch, lr, seed=0, precision="fp32", handle=None):
+    torch = _torch()
+    dev = state.device.index or 0
+    h = handle or default_handle(dev)
+    hist = np.zeros(max(epochs, 1), np.float64)
+    f32 = torch.float32
+    _check(lib().nmf_warmstart_train(h.h, _dev_ptr(state, "state", f32), _dev_ptr(X, "X", f32),
+                                     _dev_ptr(s, "s", f32), _dev_ptr(cstar, "c_star", f32),
+                                     _dev_ptr(G, "G", f32), X.shape[0], k, WS_PREC[precision],
+                                     epochs, batch, lr, seed, hist.ctypes.data, _stream(dev)))
+    return hist[:epochs]
+
+
+def ws_infer(state, X, s, k, precision="fp32", handle=None):
+    torch = _torch()
+    dev = state.device.index or 0
+    h = handle or default_handle(dev)
+    f = X.shape[0]
+    C = torch.empty((f, k), dtype=torch.float32, device=state.device)
+    f32 = torch.float32
+    _check(lib().nmf_warmstart_infer(h.h, _dev_ptr(state, "state", f32), _dev_ptr(X, "X", f32),
+                                     _dev_ptr(s, "s", f32), f, k, WS_PREC[precision], C.data_ptr(),
+                                     _stream(dev)))
+    return C

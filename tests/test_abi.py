@@ -16,7 +16,8 @@ EXPECTED = {
     "nmf_create", "nmf_destroy", "nmf_status_string", "nmf_last_error", "nmf_params_default",
     "nmf_workspace_bytes", "nmf_init_uniform", "nmf_objective", "nmf_build_basis", "nmf_project",
     "nmf_project_ragged", "nmf_subtract", "nmf_profile_enable", "nmf_profile_get",
-    "nmf_device_clock_khz",
+    "nmf_device_clock_khz", "nmf_warmstart_param_count", "nmf_warmstart_init",
+    "nmf_warmstart_pool", "nmf_warmstart_step", "nmf_warmstart_train", "nmf_warmstart_infer",
 }
 
 
@@ -176,3 +177,17 @@ def test_project_ragged_validation(L):
     assert call(C=FAKE + 12) == nmf.NMF_ERR_ARG    # C_out aliases val
     assert call() == nmf.NMF_ERR_ARG               # handle
     assert b"handle" in L.nmf_last_error()
+
+
+def test_warmstart_layout_and_validation(L):
+    assert L.nmf_warmstart_param_count(100) == 1024 * 512 + 512 + 512 * 512 + 512 + 512 * 100 + 100
+    assert L.nmf_warmstart_param_count(0) == 0
+    assert L.nmf_warmstart_init(None, None, 4, 0, None) == nmf.NMF_ERR_ARG
+    assert L.nmf_warmstart_init(None, FAKE, 0, 0, None) == nmf.NMF_ERR_ARG
+    assert L.nmf_warmstart_step(None, FAKE, FAKE, FAKE, FAKE, FAKE, 0, 4, 0, 0.0, 1, None, None,
+                                None) == nmf.NMF_ERR_SHAPE
+    assert L.nmf_warmstart_step(None, FAKE, FAKE, FAKE, FAKE, FAKE, 8, 4, 0, 1e-3, 0, None, None,
+                                None) == nmf.NMF_ERR_ARG
+    assert L.nmf_warmstart_train(None, FAKE, FAKE, FAKE, FAKE, FAKE, 100, 4, 0, 1, 8, 0.0, 0, None,
+                                 None) == nmf.NMF_ERR_ARG
+    assert L.nmf_warmstart_pool(None, FAKE, FAKE, 2, 0, 5, FAKE, FAKE, None) == nmf.NMF_ERR_SHAPE
