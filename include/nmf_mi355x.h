@@ -74,7 +74,12 @@ enum nmf_flags {
   NMF_F_BINARY_WEIGHTS = 8,  /* weights are 0/1 (enables bitmask storage)   */
   NMF_F_MASKED_GRAM = 16,    /* projection through per-frame Gram matrices  */
   NMF_F_WARM_START = 32,     /* reserved: learned warm start                */
-  NMF_F_ASYNC = 64           /* do not synchronise; report filled later     */
+  NMF_F_ASYNC = 64,          /* do not synchronise; report filled later     */
+  NMF_F_AUTOTUNE = 128       /* time candidate launch shapes of the fused
+                                passes on first use of a shape and cache the
+                                fastest in the handle (a different split
+                                changes the summation order, so results may
+                                differ in the last bits from the default)   */
 };
 
 /* Iteration parameters.  Fill with nmf_params_default() first. */
@@ -249,6 +254,11 @@ int nmf_warmstart_train(nmf_handle h, float* state, const float* X, const float*
 /* Predicted coefficients C_out (f x k) for pooled frames X, s. */
 int nmf_warmstart_infer(nmf_handle h, const float* state, const float* X, const float* s,
                         int64_t f, int32_t k, int32_t precision, float* C_out, void* stream);
+
+/* Launch shapes chosen so far by NMF_F_AUTOTUNE: writes up to cap lines of
+ * "pass n p k precision: waves pipeline splits time_us" into buf [host].
+ * Returns the number of cached entries.                                     */
+int nmf_autotune_report(nmf_handle h, char* buf, size_t cap);
 
 /* ---- live kernel timing ----------------------------------------------------
  * Opt-in instrumentation for measurement: while enabled, every kernel the

@@ -54,6 +54,12 @@ struct nmf_handle_s {
   // captured launch sequences, keyed by operation and every argument
   hipStream_t cap = nullptr;
   std::unordered_map<std::string, hipGraphExec_t> graphs;
+  // autotuned launch shapes: key -> (waves, pipeline, splits, microseconds)
+  struct Tuned {
+    int nw, pipe, splits;
+    float us;
+  };
+  std::unordered_map<std::string, Tuned> tuned;
 };
 
 namespace {
@@ -464,6 +470,72 @@ PassCfg cfg_split(int col_tiles, int RT, int KP, int req_split, int req_nw) {
   return c;
 }
 
+// Times candidate launch shapes of one fused half-step on the staged data
+// (split mode into a scratch partial buffer, so nothing the iteration reads
+// is written) and returns the fastest; cached per key in the handle.
+int autotune_pass(nmf_handle h, const std::string& key, int prec, int KP, const DualArgs& base,
+                  int col_tiles, int RT, bool allow_split, hipStream_t s, PassCfg* out) {
+  auto it = h->tuned.find(key);
+  if (it != h->tuned.end()) {
+    out->nw = it->second.nw;
+    out->pipe = it->second.pipe;
+    out->splits = it->second.splits;
+    out->tiles_per_split = (RT + out->splits - 1) / out->splits;
+    return NMF_OK;
+  }
+  std::vector<int> split_opts = {1};
+  if (allow_split)
+    for (int sp : {2, 4, 8, 16, 32, 64, 128})
+      if (sp <= RT) split_opts.push_back(sp);
+  int rc;
+  float* scratch = nullptr;
+  const int max_split = split_opts.back();
+  if ((rc = ws(h, "tune.partial", (size_t)max_split * 2 * KP * base.C_pad, &scratch))) return rc;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = 1e30f;
+  PassCfg bc = *out;
+  for (int nw : {1, 2, 4}) {
+    for (int pipe : {1, 2}) {
+      if (KP > 64 && pipe == 2) continue;
+      if (KP >= 128 && nw == 1) continue;
+      for (int sp : split_opts) {
+        const int tps = (RT + sp - 1) / sp;
+        const int S = (RT + tps - 1) / tps;
+        if (tps < nw) continue;
+        DualArgs a = base;
+        a.partial = scratch;
+        a.tiles_per_split = tps;
+        a.Jpart = nullptr;
+        const int pp = pipe_for(KP, pipe);
+        hipError_t e = launch_dual(prec, KP, MODE_SPLIT, nw, pp, a, col_tiles, S, s);
+        if (e != hipSuccess) continue;
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r) HIP_TRY(launch_dual(prec, KP, MODE_SPLIT, nw, pp, a, col_tiles, S, s));
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        // a split costs an extra finish pass over S partials: charge it
+        const float us = ms * 1e3f / 3.f + (sp > 1 ? 0.02f * S : 0.f);
+        if (us < best) {
+          best = us;
+          bc.nw = nw;
+          bc.pipe = pp;
+          bc.splits = S;
+          bc.tiles_per_split = tps;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->tuned[key] = {bc.nw, bc.pipe, bc.splits, best};
+  *out = bc;
+  return NMF_OK;
+}
+
 DualArgs pass_args(const float* D, const float* Mw, int RT, int C_pad, int C_valid, const Factor& L,
                    const float* Rt, int K, float eps) {
   DualArgs a{};
@@ -741,6 +813,15 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   DualArgs B = pass_args(DT, MwT, ptile, n_pad, (int)n, Hf, Wf.t, K, eps);
   B.tiles_per_split = cb.tiles_per_split;
   B.partial = partial;
+  if (prm->flags & NMF_F_AUTOTUNE) {
+    const std::string ka = key_of("tuneA", {(uint64_t)n, (uint64_t)p, (uint64_t)KP, (uint64_t)prec});
+    const std::string kb = key_of("tuneB", {(uint64_t)n, (uint64_t)p, (uint64_t)KP, (uint64_t)prec});
+    if ((rc = autotune_pass(h, ka, prec, KP, A, ptile, ntile, false, s, &ca))) return rc;
+    if ((rc = autotune_pass(h, kb, prec, KP, B, ntile, ptile, true, s, &cb))) return rc;
+    if ((rc = ws(h, "partial", (size_t)cb.splits * 2 * KP * n_pad, &partial))) return rc;
+    B.tiles_per_split = cb.tiles_per_split;
+    B.partial = partial;
+  }
   FinishArgs F = finish_args(partial, cb.splits, Wf, (int)n, K, eps, prec);
   F.Jpart = part;
   F.nJ = ptile;
@@ -1028,6 +1109,23 @@ int nmf_subtract(nmf_handle h, const float* H, const float* C, const float* T, c
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(prof_drain(h));
   return NMF_OK;
+}
+
+int nmf_autotune_report(nmf_handle h, char* buf, size_t cap) {
+  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+  std::string out;
+  for (const auto& kv : h->tuned) {
+    char line[256];
+    std::snprintf(line, sizeof(line), "%s: waves=%d pipeline=%d splits=%d %.2f us\n", kv.first.c_str(),
+                  kv.second.nw, kv.second.pipe, kv.second.splits, kv.second.us);
+    out += line;
+  }
+  if (buf && cap) {
+    const size_t n = std::min(cap - 1, out.size());
+    std::memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  return (int)h->tuned.size();
 }
 
 int nmf_profile_enable(nmf_handle h, int on) {

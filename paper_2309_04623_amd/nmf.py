@@ -24,7 +24,7 @@ NMF_WARN_NONMONOTONE, NMF_WARN_MAXITER = 1, 2
 
 PREC = {"fp32": 0, "bf16x3": 1}
 F_VALIDATE_DATA, F_CLIP_NEGATIVE, F_NORMALIZE_H = 1, 2, 4
-F_BINARY_WEIGHTS, F_MASKED_GRAM, F_WARM_START, F_ASYNC = 8, 16, 32, 64
+F_BINARY_WEIGHTS, F_MASKED_GRAM, F_WARM_START, F_ASYNC, F_AUTOTUNE = 8, 16, 32, 64, 128
 
 MAT_W, MAT_H, MAT_C = 0, 1, 2
 
@@ -82,6 +82,7 @@ _SIGS = {
     "nmf_warmstart_train": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32,
                                            _i32, ctypes.c_float, _u64, _dp, _vp]),
     "nmf_warmstart_infer": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]),
+    "nmf_autotune_report": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "nmf_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "nmf_profile_get": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double)]),
@@ -428,3 +429,9 @@ def ws_infer(state, X, s, k, precision="fp32", handle=None):
                                      _dev_ptr(s, "s", f32), f, k, WS_PREC[precision], C.data_ptr(),
                                      _stream(dev)))
     return C
+
+
+def autotune_report(handle: Handle) -> str:
+    buf = ctypes.create_string_buffer(8192)
+    _check(lib().nmf_autotune_report(handle.h, buf, 8192))
+    return buf.value.decode()

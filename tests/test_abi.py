@@ -18,6 +18,7 @@ EXPECTED = {
     "nmf_project_ragged", "nmf_subtract", "nmf_profile_enable", "nmf_profile_get",
     "nmf_device_clock_khz", "nmf_warmstart_param_count", "nmf_warmstart_init",
     "nmf_warmstart_pool", "nmf_warmstart_step", "nmf_warmstart_train", "nmf_warmstart_infer",
+    "nmf_autotune_report",
 }
 
 

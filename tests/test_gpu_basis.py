@@ -225,3 +225,22 @@ def test_graph_replay_matches_eager_launches():
         assert np.array_equal(Jg, Je)
         _ = torch.randn(4096, device="cuda").sum().item()
     h.close()
+
+
+def test_autotuned_shapes_give_oracle_parity():
+    """With NMF_F_AUTOTUNE the launch shapes are timed on first use and
+    cached; results still meet the FP32 bars."""
+    lib = synth.make_cfg2(n=96, ny=64, nx=64, k0=20, frames=1)
+    say("autotune")
+    h = nmf.Handle(0)
+    n, p = lib.V.shape
+    W, H, J, rep = nmf.build_basis(dev(lib.V), dev(lib.M), 16, 80, seed=2, flags=nmf.F_AUTOTUNE,
+                                   handle=h)
+    report = nmf.autotune_report(h)
+    print(report, flush=True)
+    assert report.count("\n") == 2
+    Wo, Ho, Jo = nmf64.build_basis(lib.V, lib.M, prng.init_matrix(2, 0, n, 16),
+                                   prng.init_matrix(2, 1, 16, p), 80)
+    J64 = objective64(lib.V, lib.M, host(W), host(H))
+    assert abs(J64 - Jo[-1]) / Jo[-1] <= 1e-5
+    h.close()
