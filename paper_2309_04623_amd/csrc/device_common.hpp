@@ -51,6 +51,39 @@ __host__ __device__ __forceinline__ int perm_red(int r) {
   return PREC == PREC_FP32 ? perm_f32(r) : perm_bf16(r);
 }
 
+// ---------------------------------------------------------------------------
+// Operand-ordered factor layouts.  For each aligned block of 32 rows the
+// values one MFMA operand load needs are stored as [load][lane][vector], so
+// every load instruction of a wave reads one contiguous run (1 KB).
+//   L  (rows x KP), A operand of Y = L Rt:
+//     FP32 load u (0..KP/8-1), lane i + 32h: L(r, h*KP/2 + 4u + j), j < 4
+//     BF16 load q (0..KP/16-1), lane i + 32h: L(r, 16q + 8h + e), e < 8
+//   L^T (KP x rows) with the reduction index permuted (perm_f32/perm_bf16),
+//   A operand of num/den for output tile t = k / 32:
+//     FP32 load u (0..3):  lane m + 32h holds rows 8u + 4h + j, j < 4
+//     BF16 load q (0..1):  lane m + 32h holds rows 16q + 8e' + 4h + s
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int64_t lop_f32(int r, int k, int KP) {
+  const int rb = r >> 5, i = r & 31, hk = KP >> 1;
+  const int h = k >= hk, kk = k - h * hk;
+  return (((int64_t)rb * (KP >> 3) + (kk >> 2)) * 64 + i + 32 * h) * 4 + (kk & 3);
+}
+__host__ __device__ __forceinline__ int64_t lop_bf16(int r, int k, int KP) {
+  const int rb = r >> 5, i = r & 31;
+  const int q = k >> 4, h = (k >> 3) & 1, e = k & 7;
+  return (((int64_t)rb * (KP >> 4) + q) * 64 + i + 32 * h) * 8 + e;
+}
+__host__ __device__ __forceinline__ int64_t ltop_f32(int k, int r, int KP) {
+  const int t = k >> 5, m = k & 31, rb = r >> 5, x = r & 31;
+  const int g = x >> 3, h = (x >> 2) & 1, s = x & 3;
+  return ((((int64_t)rb * (KP >> 5) + t) * 4 + g) * 64 + m + 32 * h) * 4 + s;
+}
+__host__ __device__ __forceinline__ int64_t ltop_bf16(int k, int r, int KP) {
+  const int t = k >> 5, m = k & 31, rb = r >> 5, x = r & 31;
+  const int q = x >> 4, e4 = (x >> 3) & 1, h = (x >> 2) & 1, s = x & 3;
+  return ((((int64_t)rb * (KP >> 5) + t) * 2 + q) * 64 + m + 32 * h) * 8 + 4 * e4 + s;
+}
+
 __device__ __forceinline__ f32x16 mfma_f32(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }

@@ -10,13 +10,6 @@ namespace nmf {
 // ---------------------------------------------------------------------------
 // Staging (masked pixels are missing data: Vhat = V where M > 0, else 0)
 // ---------------------------------------------------------------------------
-// Offset of element (r, c) of a 32x32 tile in MFMA accumulator order.
-__device__ __forceinline__ int tile_slot_rc(int r, int c) {
-  const int h = (r >> 2) & 1;
-  const int i = ((r >> 3) << 2) | (r & 3);
-  return (c + 32 * h) * 16 + i;
-}
-
 __global__ __launch_bounds__(256) void k_stage(StageArgs a) {
   __shared__ float tv[32][33];
   __shared__ float tm[32][33];
@@ -57,13 +50,16 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a) {
     tm[ty + 8 * q][tx] = m;
   }
   __syncthreads();
-  // Tiled copies: slot o of a tile holds (row, col) = (acc_row(o % 16, o / 512), (o / 16) % 32).
+  // Tiled copies.  Slot o of a tile holds register i of lane ln with
+  // o = (i / 4) * 256 + ln * 4 + i % 4, so that load u of a wave reads the
+  // contiguous kilobyte [u * 256, u * 256 + 256) floats; (row, col) =
+  // (acc_row(i, ln / 32), ln % 32).
   const int64_t tileA = ((int64_t)blockIdx.x * (a.n_pad / 32) + blockIdx.y) * 1024;
   const int64_t tileB = ((int64_t)blockIdx.y * (a.p_pad / 32) + blockIdx.x) * 1024;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int o = threadIdx.x + 256 * q;
-    const int ln = o >> 4, i = o & 15;
+    const int u = o >> 8, ln = (o & 255) >> 2, i = 4 * u + (o & 3);
     const int tr = acc_row(i, ln >> 5), tcol = ln & 31;
     if (a.D) {
       a.D[tileA + o] = tv[tr][tcol];
@@ -143,13 +139,13 @@ __device__ __forceinline__ void store_layouts(int r, int k, float v, int rows_pa
                                               float* tp, __bf16* tph, __bf16* tpl) {
   __bf16 hi, lo;
   split_bf16(v, hi, lo);
-  m[(int64_t)r * KP + k] = v;
-  mh[(int64_t)r * KP + k] = hi;
-  ml[(int64_t)r * KP + k] = lo;
+  m[lop_f32(r, k, KP)] = v;
+  mh[lop_bf16(r, k, KP)] = hi;
+  ml[lop_bf16(r, k, KP)] = lo;
   t[(int64_t)k * rows_pad + r] = v;
-  tp[(int64_t)k * rows_pad + perm_f32(r)] = v;
-  tph[(int64_t)k * rows_pad + perm_bf16(r)] = hi;
-  tpl[(int64_t)k * rows_pad + perm_bf16(r)] = lo;
+  tp[ltop_f32(k, r, KP)] = v;
+  tph[ltop_bf16(k, r, KP)] = hi;
+  tpl[ltop_bf16(k, r, KP)] = lo;
 }
 
 __global__ __launch_bounds__(256) void k_factor_fill(FactorFillArgs a) {
@@ -220,16 +216,16 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs a) {
     const int64_t it = (int64_t)k * a.C_pad + c;
     if (k < a.K && c < a.C_valid) nv = mu_apply_d(a.t[it], num, den, a.eps);
     a.t[it] = nv;
-    a.m[(int64_t)c * a.KP + k] = nv;
+    a.m[lop_f32(c, k, a.KP)] = nv;
     if (a.prec == PREC_FP32) {
-      a.tp[(int64_t)k * a.C_pad + perm_f32(c)] = nv;
+      a.tp[ltop_f32(k, c, a.KP)] = nv;
     } else {
       __bf16 hi, lo;
       split_bf16(nv, hi, lo);
-      a.mh[(int64_t)c * a.KP + k] = hi;
-      a.ml[(int64_t)c * a.KP + k] = lo;
-      a.tph[(int64_t)k * a.C_pad + perm_bf16(c)] = hi;
-      a.tpl[(int64_t)k * a.C_pad + perm_bf16(c)] = lo;
+      a.mh[lop_bf16(c, k, a.KP)] = hi;
+      a.ml[lop_bf16(c, k, a.KP)] = lo;
+      a.tph[ltop_bf16(k, c, a.KP)] = hi;
+      a.tpl[ltop_bf16(k, c, a.KP)] = lo;
     }
   }
   if (a.Jpart && blockIdx.x == 0 && blockIdx.y == 0) {

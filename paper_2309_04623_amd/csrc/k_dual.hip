@@ -6,8 +6,9 @@
 // For every 32x32 tile a wave
 //   1. forms Y = L[rows] * Rt[:, cols] on MFMA (the model W H, Eq. 1),
 //   2. reads D and the weights Mw for the same tile, stored in MFMA
-//      accumulator order so that each lane fetches its 16 values with four
-//      16-byte loads (the next tile is prefetched while this one computes),
+//      accumulator order so that the wave fetches them with four fully
+//      coalesced 16-byte-per-lane loads (the next tile is prefetched while
+//      this one computes),
 //      and forms A = Mw o D, Z = Mw o Y and the residual term Mw (D - Y)^2
 //      (Eq. 2),
 //   3. accumulates num += L^T A and den += L^T Z on MFMA, fed straight from
@@ -35,10 +36,13 @@
 
 namespace nmf {
 
+// p points at lane * 4 floats inside a 1024-float tile; load u reads floats
+// [u * 256 + lane * 4, +4), so each load instruction covers one contiguous
+// kilobyte.
 __device__ __forceinline__ void load_tile(const float* p, f32x4 (&v)[4]) {
   const f32x4* q = reinterpret_cast<const f32x4*>(p);
 #pragma unroll
-  for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(q + u);
+  for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(q + 64 * u);
 }
 
 // Operand registers of one 32-row tile: the L rows (A operand of Y = L Rt)
@@ -56,47 +60,51 @@ struct Ops {
   bf16x8 th[NT_BF], tl[NT_BF];
 };
 
+// Operand loads read the operand-ordered factor layouts (lop_*, ltop_*):
+// one contiguous kilobyte per load instruction.
 template <int PREC, int KP>
-__device__ __forceinline__ void load_l(Ops<PREC, KP>& o, const DualArgs& a, int r0, int col,
-                                       int half) {
+__device__ __forceinline__ void load_l(Ops<PREC, KP>& o, const DualArgs& a, int r0, int lane) {
+  const int64_t rb = r0 >> 5;
   if constexpr (PREC == PREC_FP32) {
-    const f32x4* lp = reinterpret_cast<const f32x4*>(a.L + (int64_t)(r0 + col) * KP + half * (KP / 2));
+    const f32x4* lp = reinterpret_cast<const f32x4*>(a.L + rb * (KP / 8) * 256) + lane;
 #pragma unroll
-    for (int u = 0; u < KP / 8; ++u) o.lq[u] = lp[u];
+    for (int u = 0; u < KP / 8; ++u) o.lq[u] = lp[64 * u];
   } else {
-    const bf16x8* lph = reinterpret_cast<const bf16x8*>(a.Lh + (int64_t)(r0 + col) * KP + 8 * half);
-    const bf16x8* lpl = reinterpret_cast<const bf16x8*>(a.Ll + (int64_t)(r0 + col) * KP + 8 * half);
+    const bf16x8* lph = reinterpret_cast<const bf16x8*>(a.Lh + rb * (KP / 16) * 512) + lane;
+    const bf16x8* lpl = reinterpret_cast<const bf16x8*>(a.Ll + rb * (KP / 16) * 512) + lane;
 #pragma unroll
-    for (int j = 0; j < KP / 16; ++j) {
-      o.lh[j] = lph[2 * j];
-      o.ll[j] = lpl[2 * j];
+    for (int q = 0; q < KP / 16; ++q) {
+      o.lh[q] = lph[64 * q];
+      o.ll[q] = lpl[64 * q];
     }
   }
 }
 
 template <int PREC, int KP>
-__device__ __forceinline__ void load_lt_tile(Ops<PREC, KP>& o, const DualArgs& a, int r0, int col,
-                                             int half, int t) {
+__device__ __forceinline__ void load_lt_tile(Ops<PREC, KP>& o, const DualArgs& a, int r0, int lane,
+                                             int t) {
+  constexpr int MT = KP / 32;
+  const int64_t blk = (int64_t)(r0 >> 5) * MT + t;
   if constexpr (PREC == PREC_FP32) {
-    const f32x4* lt = reinterpret_cast<const f32x4*>(a.LT + (int64_t)(32 * t + col) * a.ldlt + r0 + 16 * half);
+    const f32x4* lt = reinterpret_cast<const f32x4*>(a.LT + blk * 1024) + lane;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) o.tq[4 * t + u] = lt[u];
+    for (int u = 0; u < 4; ++u) o.tq[4 * t + u] = lt[64 * u];
   } else {
-    const int64_t off = (int64_t)(32 * t + col) * a.ldlt + r0 + 8 * half;
+    const bf16x8* lh = reinterpret_cast<const bf16x8*>(a.LTh + blk * 1024) + lane;
+    const bf16x8* ll = reinterpret_cast<const bf16x8*>(a.LTl + blk * 1024) + lane;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      o.th[2 * t + j] = *reinterpret_cast<const bf16x8*>(a.LTh + off + 16 * j);
-      o.tl[2 * t + j] = *reinterpret_cast<const bf16x8*>(a.LTl + off + 16 * j);
+    for (int q = 0; q < 2; ++q) {
+      o.th[2 * t + q] = lh[64 * q];
+      o.tl[2 * t + q] = ll[64 * q];
     }
   }
 }
 
 template <int PREC, int KP>
-__device__ __forceinline__ void load_ops(Ops<PREC, KP>& o, const DualArgs& a, int r0, int col,
-                                         int half) {
-  load_l<PREC, KP>(o, a, r0, col, half);
+__device__ __forceinline__ void load_ops(Ops<PREC, KP>& o, const DualArgs& a, int r0, int lane) {
+  load_l<PREC, KP>(o, a, r0, lane);
 #pragma unroll
-  for (int t = 0; t < KP / 32; ++t) load_lt_tile<PREC, KP>(o, a, r0, col, half, t);
+  for (int t = 0; t < KP / 32; ++t) load_lt_tile<PREC, KP>(o, a, r0, lane, t);
 }
 
 template <int PREC, int KP, int MODE, int NW, int PIPE>
@@ -148,14 +156,14 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
   double jacc = 0.0;
 
   const int64_t tile_base = (int64_t)tc * a.RT;
-  const float* dcol = a.D + tile_base * 1024 + lane * 16;
-  const float* mcol = a.Mw + tile_base * 1024 + lane * 16;
+  const float* dcol = a.D + tile_base * 1024 + lane * 4;
+  const float* mcol = a.Mw + tile_base * 1024 + lane * 4;
   // PIPE 0: operands loaded at their use (large KP); PIPE 1: all operands of
   // a tile loaded at its start; PIPE 2: operands and data of the wave's next
   // tile loaded one tile ahead, so every wait covers loads issued a full
   // tile earlier.
   using O = Ops<PREC, KP>;
-  const auto ops_for = [&](O& o, int r0) { load_ops<PREC, KP>(o, a, r0, col, half); };
+  const auto ops_for = [&](O& o, int r0) { load_ops<PREC, KP>(o, a, r0, lane); };
 
   // One tile: consume (dv, mv, oc); prefetch the wave's next tile's data into
   // (dn, mn) and, with PIPE 2, its operands into on.
@@ -177,7 +185,7 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
 
     // ---- Y = L[r0:r0+32, :] * Rt ------------------------------------------
     f32x16 y = zero16();
-    if constexpr (PIPE == 0) load_l<PREC, KP>(oc, a, r0, col, half);
+    if constexpr (PIPE == 0) load_l<PREC, KP>(oc, a, r0, lane);
     if constexpr (PREC == PREC_FP32) {
 #pragma unroll
       for (int u = 0; u < KP / 8; ++u) {
@@ -212,7 +220,7 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
       if constexpr (PREC == PREC_FP32) {
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
-          if constexpr (PIPE == 0) load_lt_tile<PREC, KP>(oc, a, r0, col, half, t);
+          if constexpr (PIPE == 0) load_lt_tile<PREC, KP>(oc, a, r0, lane, t);
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             num[t] = mfma_f32(oc.tq[4 * t + (i >> 2)][i & 3], av[i], num[t]);
@@ -236,7 +244,7 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
         }
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
-          if constexpr (PIPE == 0) load_lt_tile<PREC, KP>(oc, a, r0, col, half, t);
+          if constexpr (PIPE == 0) load_lt_tile<PREC, KP>(oc, a, r0, lane, t);
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
             num[t] = mfma_bf16x3(oc.th[2 * t + j], oc.tl[2 * t + j], ah[j], al[j], num[t]);
@@ -330,15 +338,15 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
         if (cval && k < a.K) nv = mu_apply(old[i], num[t][i], den[t][i], a.eps);
         a.Rt_out[(int64_t)k * a.ldr + c] = nv;
         if constexpr (PREC == PREC_FP32) {
-          a.RtT[(int64_t)c * KP + k] = nv;
-          a.Rtp[(int64_t)k * a.ldr + perm_f32(c)] = nv;
+          a.RtT[lop_f32(c, k, KP)] = nv;
+          a.Rtp[ltop_f32(k, c, KP)] = nv;
         } else {
           __bf16 hi, lo;
           split_bf16(nv, hi, lo);
-          a.RtTh[(int64_t)c * KP + k] = hi;
-          a.RtTl[(int64_t)c * KP + k] = lo;
-          a.Rtph[(int64_t)k * a.ldr + perm_bf16(c)] = hi;
-          a.Rtpl[(int64_t)k * a.ldr + perm_bf16(c)] = lo;
+          a.RtTh[lop_bf16(c, k, KP)] = hi;
+          a.RtTl[lop_bf16(c, k, KP)] = lo;
+          a.Rtph[ltop_bf16(k, c, KP)] = hi;
+          a.Rtpl[ltop_bf16(k, c, KP)] = lo;
         }
       }
     }

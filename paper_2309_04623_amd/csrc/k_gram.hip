@@ -74,7 +74,6 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       tmj[q] = -1;
     }
   }
-  const f32x4* HT4 = reinterpret_cast<const f32x4*>(a.HT);
   f32x4* Hs4 = reinterpret_cast<f32x4*>(Hs);
   const uint64_t key = sm_key(a.seed, 2);
   int bad = 0;
@@ -134,7 +133,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
           } else {
             prow = (int)jj;
           }
-          if (prow >= 0) v = HT4[(int64_t)prow * KQ + kq];
+          if (prow >= 0) v = *reinterpret_cast<const f32x4*>(a.HT + lop_f32(prow, 4 * kq, KP));
         }
         Hs4[x] = v;
       }

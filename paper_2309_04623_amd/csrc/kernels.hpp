@@ -16,20 +16,20 @@ namespace nmf {
 // the same step on the transposed problem (D = V^T, L = H^T, Rt = W^T).
 //
 // D and Mw are stored tiled: 32x32 tiles, column-tile-major (tile (tr, tc)
-// at index tc * RT + tr), and inside a tile in MFMA accumulator order: the
-// 16 values of lane l (column l % 32, rows acc_row(i, l / 32)) at
-// l * 16 + i.
+// at index tc * RT + tr), and inside a tile in MFMA accumulator order:
+// register i of lane l (column l % 32, row acc_row(i, l / 32)) at
+// (i / 4) * 256 + l * 4 + i % 4.
 struct DualArgs {
   const float* D;
   const float* Mw;
   int RT;               // row tiles (R_pad / 32)
   int tiles_per_split;  // row tiles per grid-y chunk
   int C_pad, C_valid;
-  // left factor rows (R_pad x KP): FP32, or the bf16 hi/lo split
+  // left factor rows (R_pad x KP) in the operand order lop_f32 / lop_bf16
   const float* L;
   const __bf16* Lh;
   const __bf16* Ll;
-  // left factor transposed (KP x R_pad), reduction index permuted per 32-block
+  // left factor transposed (KP x R_pad) in the operand order ltop_f32 / ltop_bf16
   const float* LT;
   const __bf16* LTh;
   const __bf16* LTl;
@@ -154,7 +154,7 @@ hipError_t launch_frame_objective(const float* H, const float* C, const float* T
 
 // Masked-Gram projection: one persistent launch over all frames.
 struct GramArgs {
-  const float* HT;  // P_pad x KP, row per pixel (H transposed)
+  const float* HT;  // H transposed (P_pad x KP) in the lop_f32 operand order
   int K, P, F;
   // dense frames (F x P), or CSR frames
   const float* T;
