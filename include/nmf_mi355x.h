@@ -96,8 +96,10 @@ typedef struct {
   int32_t split;         /* row chunks of the split half-step; 0 = auto      */
   int32_t waves;         /* waves per workgroup of the fused passes (1, 2, 4);
                             0 = auto                                          */
-  int32_t pipeline;      /* operand pipelining of the fused passes: 1 = per
-                            tile, 2 = one tile ahead (k <= 64); 0 = auto      */
+  int32_t pipeline;      /* load pipelining of the fused passes: 1 = operands
+                            per tile, 2 = operands and data one tile ahead,
+                            3 = operands one and data two tiles ahead
+                            (2 and 3 for k <= 64); 0 = auto                   */
 } nmf_params;
 
 /* Filled by the calls that iterate.  [host] */

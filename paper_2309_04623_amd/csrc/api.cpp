@@ -286,7 +286,7 @@ int check_params(const nmf_params* prm, int64_t rows, int64_t cols, bool need_k_
   if (prm->split < 0) return fail(NMF_ERR_ARG, "split must be >= 0");
   if (prm->waves != 0 && prm->waves != 1 && prm->waves != 2 && prm->waves != 4)
     return fail(NMF_ERR_ARG, "waves must be 0, 1, 2 or 4");
-  if (prm->pipeline < 0 || prm->pipeline > 2) return fail(NMF_ERR_ARG, "pipeline must be 0, 1 or 2");
+  if (prm->pipeline < 0 || prm->pipeline > 3) return fail(NMF_ERR_ARG, "pipeline must be 0..3");
   return NMF_OK;
 }
 
@@ -497,8 +497,8 @@ int autotune_pass(nmf_handle h, const std::string& key, int prec, int KP, const 
   float best = 1e30f;
   PassCfg bc = *out;
   for (int nw : {1, 2, 4}) {
-    for (int pipe : {1, 2}) {
-      if (KP > 64 && pipe == 2) continue;
+    for (int pipe : {1, 2, 3}) {
+      if (KP > 64 && pipe >= 2) continue;
       if (KP >= 128 && nw == 1) continue;
       for (int sp : split_opts) {
         const int tps = (RT + sp - 1) / sp;

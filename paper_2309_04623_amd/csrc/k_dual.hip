@@ -161,8 +161,9 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
   // PIPE 0: operands loaded at their use (large KP); PIPE 1: all operands of
   // a tile loaded at its start; PIPE 2: operands and data of the wave's next
   // tile loaded one tile ahead, so every wait covers loads issued a full
-  // tile earlier.
+  // tile earlier; PIPE 3: as 2 with the data two tiles ahead.
   using O = Ops<PREC, KP>;
+  constexpr int PFD = PIPE == 3 ? 2 : 1;  // data prefetch distance in tiles
   const auto ops_for = [&](O& o, int r0) { load_ops<PREC, KP>(o, a, r0, lane); };
 
   // One tile: consume (dv, mv, oc); prefetch the wave's next tile's data into
@@ -170,17 +171,18 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
   auto step = [&](const int tr, const f32x4 (&dv)[4], const f32x4 (&mv)[4], O& oc, f32x4 (&dn)[4],
                   f32x4 (&mn)[4], O& on) {
     const int r0 = tr * TILE;
-    // Unconditional (the last step re-reads its own tile) so that the number
-    // of loads in flight is static and the waits below stay precise.
+    // Unconditional (past the end a step re-reads its own tile) so that the
+    // number of loads in flight is static and the waits below stay precise.
     const int trn = (tr + NW < t_end) ? tr + NW : tr;
-    if constexpr (PIPE == 2) {
+    const int trd = (tr + PFD * NW < t_end) ? tr + PFD * NW : tr;
+    if constexpr (PIPE >= 2) {
       ops_for(on, trn * TILE);
     } else if constexpr (PIPE == 1) {
       ops_for(oc, r0);
     }
     __builtin_amdgcn_sched_barrier(0);
-    load_tile(dcol + (int64_t)trn * 1024, dn);
-    load_tile(mcol + (int64_t)trn * 1024, mn);
+    load_tile(dcol + (int64_t)trd * 1024, dn);
+    load_tile(mcol + (int64_t)trd * 1024, mn);
     __builtin_amdgcn_sched_barrier(0);
 
     // ---- Y = L[r0:r0+32, :] * Rt ------------------------------------------
@@ -256,17 +258,44 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
   };
 
   int tr = t_begin + wave;
-  f32x4 dA[4], mA[4], dB[4], mB[4];
-  O oA, oB;
-  if (tr < t_end) {
-    if constexpr (PIPE == 2) ops_for(oA, tr * TILE);
-    load_tile(dcol + (int64_t)tr * 1024, dA);
-    load_tile(mcol + (int64_t)tr * 1024, mA);
-  }
-  for (; tr < t_end; tr += 2 * NW) {
-    step(tr, dA, mA, oA, dB, mB, oB);
-    if (tr + NW >= t_end) break;
-    step(tr + NW, dB, mB, oB, dA, mA, oA);
+  if constexpr (PFD == 1) {
+    f32x4 dA[4], mA[4], dB[4], mB[4];
+    O oA, oB;
+    if (tr < t_end) {
+      if constexpr (PIPE >= 2) ops_for(oA, tr * TILE);
+      load_tile(dcol + (int64_t)tr * 1024, dA);
+      load_tile(mcol + (int64_t)tr * 1024, mA);
+    }
+    for (; tr < t_end; tr += 2 * NW) {
+      step(tr, dA, mA, oA, dB, mB, oB);
+      if (tr + NW >= t_end) break;
+      step(tr + NW, dB, mB, oB, dA, mA, oA);
+    }
+  } else {
+    // data two tiles ahead: three data buffers, two operand sets
+    f32x4 dA[4], mA[4], dB[4], mB[4], dC[4], mC[4];
+    O oA, oB;
+    if (tr < t_end) {
+      ops_for(oA, tr * TILE);
+      load_tile(dcol + (int64_t)tr * 1024, dA);
+      load_tile(mcol + (int64_t)tr * 1024, mA);
+      const int t1 = (tr + NW < t_end) ? tr + NW : tr;
+      load_tile(dcol + (int64_t)t1 * 1024, dB);
+      load_tile(mcol + (int64_t)t1 * 1024, mB);
+    }
+    for (; tr < t_end; tr += 6 * NW) {
+      step(tr, dA, mA, oA, dC, mC, oB);
+      if (tr + NW >= t_end) break;
+      step(tr + NW, dB, mB, oB, dA, mA, oA);
+      if (tr + 2 * NW >= t_end) break;
+      step(tr + 2 * NW, dC, mC, oA, dB, mB, oB);
+      if (tr + 3 * NW >= t_end) break;
+      step(tr + 3 * NW, dA, mA, oB, dC, mC, oA);
+      if (tr + 4 * NW >= t_end) break;
+      step(tr + 4 * NW, dB, mB, oA, dA, mA, oB);
+      if (tr + 5 * NW >= t_end) break;
+      step(tr + 5 * NW, dC, mC, oB, dB, mB, oA);
+    }
   }
 
   // ---- combine the NW waves' sums in a fixed order -----------------------
@@ -367,6 +396,7 @@ static hipError_t launch_nw(int nw, const DualArgs& a, dim3 g, hipStream_t s) {
 template <int PREC, int KP, int MODE>
 static hipError_t launch_mode(int nw, int pipe, const DualArgs& a, dim3 g, hipStream_t s) {
   if constexpr (KP <= 64) {
+    if (pipe == 3) return launch_nw<PREC, KP, MODE, 3>(nw, a, g, s);
     if (pipe == 2) return launch_nw<PREC, KP, MODE, 2>(nw, a, g, s);
     return launch_nw<PREC, KP, MODE, 1>(nw, a, g, s);
   } else {
