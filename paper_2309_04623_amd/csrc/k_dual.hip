@@ -336,9 +336,8 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
       a.Jpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
     }
   }
-  if (wave != 0) return;
-
   if constexpr (MODE == MODE_SPLIT) {
+    if (wave != 0) return;
     float* pn = a.partial + (int64_t)blockIdx.y * 2 * KP * a.C_pad;
     float* pd = pn + (int64_t)KP * a.C_pad;
 #pragma unroll
@@ -353,29 +352,59 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
   }
 
   if constexpr (MODE == MODE_UPDATE) {
-    const int c = c0 + col;
-    const bool cval = c < a.C_valid;
+    // Wave 0 applies the update and writes the KP x C layout (coalesced per
+    // row); the new 32 x KP tile is staged in LDS so that all waves write
+    // the operand-ordered copies the other half-step reads as contiguous
+    // chunks (this tile's 32 columns own exactly one chunk of each).
+    __shared__ float stage[32][KP + 1];
+    if (wave == 0) {
+      const int c = c0 + col;
+      const bool cval = c < a.C_valid;
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      float old[16];
+      for (int t = 0; t < MT; ++t) {
+        float old[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) old[i] = a.Rt[(int64_t)(32 * t + acc_row(i, half)) * a.ldr + c];
+        for (int i = 0; i < 16; ++i) old[i] = a.Rt[(int64_t)(32 * t + acc_row(i, half)) * a.ldr + c];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int k = 32 * t + acc_row(i, half);
-        float nv = 0.f;
-        if (cval && k < a.K) nv = mu_apply(old[i], num[t][i], den[t][i], a.eps);
-        a.Rt_out[(int64_t)k * a.ldr + c] = nv;
-        if constexpr (PREC == PREC_FP32) {
-          a.RtT[lop_f32(c, k, KP)] = nv;
-          a.Rtp[ltop_f32(k, c, KP)] = nv;
-        } else {
-          __bf16 hi, lo;
-          split_bf16(nv, hi, lo);
-          a.RtTh[lop_bf16(c, k, KP)] = hi;
-          a.RtTl[lop_bf16(c, k, KP)] = lo;
-          a.Rtph[ltop_bf16(k, c, KP)] = hi;
-          a.Rtpl[ltop_bf16(k, c, KP)] = lo;
+        for (int i = 0; i < 16; ++i) {
+          const int k = 32 * t + acc_row(i, half);
+          float nv = 0.f;
+          if (cval && k < a.K) nv = mu_apply(old[i], num[t][i], den[t][i], a.eps);
+          a.Rt_out[(int64_t)k * a.ldr + c] = nv;
+          stage[col][k] = nv;
+        }
+      }
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)tc * 32 * KP;
+    for (int o = threadIdx.x; o < 32 * KP; o += 64 * NW) {
+      if constexpr (PREC == PREC_FP32) {
+        {  // lop_f32 chunk: o = (u * 64 + lane) * 4 + j
+          const int ln = (o >> 2) & 63, u = o >> 8, j = o & 3;
+          const int k = (ln >> 5) * (KP / 2) + 4 * u + j;
+          a.RtT[base + o] = stage[ln & 31][k];
+        }
+        {  // ltop_f32 chunk: o = ((t * 4 + g) * 64 + lane) * 4 + s
+          const int t = o >> 10, g = (o >> 8) & 3, ln = (o >> 2) & 63, sx = o & 3;
+          const int k = 32 * t + (ln & 31), x = 8 * g + 4 * (ln >> 5) + sx;
+          a.Rtp[base + o] = stage[x][k];
+        }
+      } else {
+        __bf16 hi, lo;
+        {  // lop_bf16 chunk: o = (q * 64 + lane) * 8 + e
+          const int q = o >> 9, ln = (o >> 3) & 63, e = o & 7;
+          const int k = 16 * q + 8 * (ln >> 5) + e;
+          split_bf16(stage[ln & 31][k], hi, lo);
+          a.RtTh[base + o] = hi;
+          a.RtTl[base + o] = lo;
+        }
+        {  // ltop_bf16 chunk: o = ((t * 2 + q) * 64 + lane) * 8 + e
+          const int t = o >> 10, q = (o >> 9) & 1, ln = (o >> 3) & 63, e = o & 7;
+          const int k = 32 * t + (ln & 31);
+          const int x = 16 * q + 8 * (e >> 2) + 4 * (ln >> 5) + (e & 3);
+          split_bf16(stage[x][k], hi, lo);
+          a.Rtph[base + o] = hi;
+          a.Rtpl[base + o] = lo;
         }
       }
     }
