@@ -5,13 +5,16 @@ Workload (STIS-shaped, synthetic): a reference library of N = 500 images of
 200 x 200 px (P = 40000) with a 12 px diagonal occulting wedge and weights
 1/(V + 0.01); a K = 30 basis is built with 1000 iterations of Eq. 3, then 50
 science frames (with injected ring disks at 1e-3) are projected onto it for
-1000 iterations and the model PSF is subtracted.  One step = all of that.
+1000 iterations (masked-Gram form, one persistent launch) and the model PSF
+is subtracted.  One step = all of that.
 
 Prints one JSON line.  ``value`` = basis iterations per second of the whole
 step (1000 / step time); the line also carries the GEMM TFLOP/s of the
 fused half-step kernels, projection frames/s, a ``roofline`` object for the
-dominant kernel (timed live with HIP events on the library's stream) and a
-``cpu_baseline`` object (the FP64 oracle on this host's cores).
+dominant kernel (timed live with HIP events on the library's stream), the
+same figures for the other precision form under ``precision_forms`` (FP32
+and split-precision bf16x3), and a ``cpu_baseline`` object (the FP64 oracle
+on this host's cores).
 """
 from __future__ import annotations
 
@@ -76,6 +79,12 @@ def main():
     ap.add_argument("--proj-iters", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--single-precision", action="store_true",
+                    help="time only --precision (by default the other precision form is "
+                         "timed too and reported under precision_forms)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain elementwise copy of MIB MiB (reads and writes "
+                         "MIB MiB), the reference dispatch for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -101,70 +110,101 @@ def main():
     T = torch.from_numpy(lib.T).to(dev)
     MT = torch.from_numpy(lib.MT).to(dev)
     h = nmf.Handle(0)
+    if args.copy_calibration > 0:
+        nel = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(nel, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"calibration copy of {args.copy_calibration} MiB done")
 
-    def step():
-        W, H, J, rep = nmf.build_basis(V, M, K, args.iters, precision=args.precision, seed=1,
-                                       handle=h)
-        C, _ = nmf.project(H, T, MT, args.proj_iters, precision=args.precision, seed=2, handle=h)
+    def step(prec):
+        W, H, J, rep = nmf.build_basis(V, M, K, args.iters, precision=prec, seed=1, handle=h)
+        C, _ = nmf.project(H, T, MT, args.proj_iters, precision=prec, seed=2, gram=True,
+                           handle=h)
         model, resid = nmf.subtract(H, C, T, MT, handle=h)
         return J, rep
 
-    for i in range(args.warmup):
-        log(f"warmup step {i + 1}/{args.warmup}")
-        step()
-    torch.cuda.synchronize()
-    nmf.profile_enable(h, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        J, rep = step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    prof = {K_NAMES[c]: nmf.profile_get(h, c) for c in range(7)}
-    nmf.profile_enable(h, False)
-    log(f"timed {args.steps} steps: {el:.3f} s; final J {J[-1]:.6e} rel {rep['objective_rel']:.3e}")
+    def measure(prec):
+        """Warm-up, then exactly ``steps`` timed steps bracketed by device
+        synchronisation; kernel time per launch class from the library's
+        own HIP events on its stream."""
+        for i in range(args.warmup):
+            log(f"[{prec}] warmup step {i + 1}/{args.warmup}")
+            step(prec)
+        torch.cuda.synchronize()
+        nmf.profile_enable(h, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            J, rep = step(prec)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = {K_NAMES[c]: nmf.profile_get(h, c) for c in range(7)}
+        nmf.profile_enable(h, False)
+        log(f"[{prec}] timed {args.steps} steps: {el:.3f} s; final J {J[-1]:.6e} "
+            f"rel {rep['objective_rel']:.3e}")
+        return el, prof
 
-    ms_per_step = el * 1e3 / args.steps
-    iters_per_s = args.iters * args.steps / el
-    # algorithmic work of one basis iteration: six N x K x P contractions
-    flops_iter = 12.0 * n * K * p
-    gemm_ms = prof["hrule"][1] + prof["wrule"][1]
-    gemm_tflops = flops_iter * args.iters * args.steps / (gemm_ms * 1e-3) / 1e12
-    basis_ms = sum(prof[c][1] for c in ("hrule", "wrule", "wfinish", "objective"))
-    proj_ms = prof["project"][1] + prof["subtract"][1]
-    frames_per_s = f * args.steps / (proj_ms * 1e-3) if proj_ms > 0 else None
+    def summarize(prec, el, prof):
+        # algorithmic work of one basis iteration: six N x K x P contractions
+        flops_iter = 12.0 * n * K * p
+        gemm_ms = prof["hrule"][1] + prof["wrule"][1]
+        basis_ms = sum(prof[c][1] for c in ("hrule", "wrule", "wfinish", "objective"))
+        proj_ms = prof["project"][1] + prof["subtract"][1]
+        # Dominant kernel: the fused half-step with the larger summed time.
+        dom = max(("hrule", "wrule"), key=lambda c: prof[c][1])
+        cnt, tot = prof[dom]
+        avg_s = tot * 1e-3 / cnt
+        # per launch: 3 N K P multiply-adds (Y, num, den), and the data stream
+        # (value + weight, 8 B per element) plus the factors read and written
+        flops = 6.0 * n * K * p
+        bytes_ = 8.0 * n * p + 4.0 * (n * K + 2 * K * p) if dom == "hrule" else \
+            8.0 * n * p + 4.0 * (2 * n * K + K * p)
+        peak_fl = PEAK_FP32_TFLOPS if prec == "fp32" else PEAK_BF16_TFLOPS / 3
+        t_mfma = flops / (peak_fl * 1e12)
+        t_hbm = bytes_ / (PEAK_HBM_GBS * 1e9)
+        if t_mfma >= t_hbm:
+            roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": peak_fl,
+                    "unit": "TFLOP/s"}
+        else:
+            roof = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        roof["traffic"] = None
+        roof["kernel"] = f"k_dual ({dom} half-step), avg {avg_s * 1e6:.2f} us over {cnt} launches"
+        roof["hbm_GBs_algorithmic"] = bytes_ / avg_s / 1e9
+        roof["mfma_TFLOPs_algorithmic"] = flops / avg_s / 1e12
+        return {
+            "iterations_per_s": args.iters * args.steps / el,
+            "ms_per_step": el * 1e3 / args.steps,
+            "gemm_tflops": flops_iter * args.iters * args.steps / (gemm_ms * 1e-3) / 1e12,
+            "basis_iters_per_s_device": args.iters * args.steps / (basis_ms * 1e-3),
+            "frames_per_s": f * args.steps / (proj_ms * 1e-3) if proj_ms > 0 else None,
+            "kernel_ms_per_step": {c: prof[c][1] / args.steps for c in K_NAMES},
+            "kernel_launches_per_step": {c: prof[c][0] // args.steps for c in K_NAMES},
+            "roofline": roof,
+        }
 
-    # Dominant kernel: the fused half-step with the larger summed time.
-    dom = max(("hrule", "wrule"), key=lambda c: prof[c][1])
-    cnt, tot = prof[dom]
-    avg_s = tot * 1e-3 / cnt
-    # per launch: 3 N K P multiply-adds (Y, num, den), and the data stream
-    # (value + weight, 8 B per element) plus the factors read and written
-    flops = 6.0 * n * K * p
-    bytes_ = 8.0 * n * p + 4.0 * (n * K + 2 * K * p) if dom == "hrule" else \
-        8.0 * n * p + 4.0 * (2 * n * K + K * p)
-    peak_fl = PEAK_FP32_TFLOPS if args.precision == "fp32" else PEAK_BF16_TFLOPS / 3
-    t_mfma = flops / (peak_fl * 1e12)
-    t_hbm = bytes_ / (PEAK_HBM_GBS * 1e9)
-    if t_mfma >= t_hbm:
-        roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": peak_fl,
-                "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": PEAK_HBM_GBS,
-                "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = f"k_dual ({dom} half-step), avg {avg_s * 1e6:.2f} us over {cnt} launches"
-    roof["hbm_GBs_algorithmic"] = bytes_ / avg_s / 1e9
+    main_sum = summarize(args.precision, *measure(args.precision))
+    others = {}
+    if not args.single_precision:
+        for prec in ("fp32", "bf16x3"):
+            if prec != args.precision:
+                others[prec] = summarize(prec, *measure(prec))
+        for o in others.values():
+            o["roofline"].pop("traffic", None)
 
     out = {
         "metric": METRIC,
-        "value": iters_per_s,
+        "value": main_sum["iterations_per_s"],
         "unit": "iterations/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": main_sum["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -173,14 +213,13 @@ def main():
         "config": {"workload": "STIS-shaped basis build + projection + subtraction",
                    "images": n, "pixels": p, "image_shape": [200, 200], "k": K,
                    "basis_iters": args.iters, "frames": f, "proj_iters": args.proj_iters,
-                   "precision": args.precision},
-        "gemm_tflops": gemm_tflops,
-        "basis_iters_per_s_device": args.iters * args.steps / (basis_ms * 1e-3),
-        "frames_per_s": frames_per_s,
-        "kernel_ms_per_step": {c: prof[c][1] / args.steps for c in K_NAMES},
-        "kernel_launches_per_step": {c: prof[c][0] // args.steps for c in K_NAMES},
-        "roofline": roof,
+                   "projection": "masked-Gram", "precision": args.precision},
     }
+    for key in ("gemm_tflops", "basis_iters_per_s_device", "frames_per_s", "kernel_ms_per_step",
+                "kernel_launches_per_step", "roofline"):
+        out[key] = main_sum[key]
+    if others:
+        out["precision_forms"] = others
     if not args.no_cpu_baseline:
         log(f"timing the FP64 oracle on host cores for ~{args.cpu_seconds:.0f} s ...")
         out["cpu_baseline"] = cpu_baseline(lib, K, args.cpu_seconds)

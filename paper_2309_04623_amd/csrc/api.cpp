@@ -438,13 +438,20 @@ int pipe_for(int KP, int req) { return KP > 64 ? 0 : (req > 0 ? req : 2); }
 int occupancy_for(int KP) { return KP <= 64 ? 2 : 1; }
 constexpr int SIMDS = 1024;  // 256 compute units x 4
 
-PassCfg cfg_whole(int col_tiles, int RT, int KP, int req_nw) {
+// Default launch shapes (measured on the STIS-shaped workload, 500 x 40000,
+// K = 30): the update pass runs four waves per workgroup in FP32 and one in
+// bf16x3 (whose fused kernel then stays at two waves per SIMD); the split pass
+// takes about one workgroup per compute unit, four waves (FP32) or two
+// (bf16x3).  The autotuner replaces these per shape on request.
+PassCfg cfg_whole(int col_tiles, int RT, int KP, int prec, int req_nw) {
   PassCfg c;
   const int cap = SIMDS * occupancy_for(KP);
   c.nw = KP >= 128 ? 2 : 1;  // one wave per workgroup spills at KP = 128
   if (req_nw > 0) {
     c.nw = req_nw;
-  } else {
+  } else if (KP <= 64 && prec == NMF_PREC_FP32 && RT >= 4) {
+    c.nw = 4;
+  } else if (KP > 64) {
     for (int nw : {4, 2}) {
       if ((int64_t)col_tiles * nw <= cap && RT >= nw) {
         c.nw = nw;
@@ -454,15 +461,14 @@ PassCfg cfg_whole(int col_tiles, int RT, int KP, int req_nw) {
   }
   c.splits = 1;
   c.tiles_per_split = RT;
-  c.pipe = pipe_for(KP, 0);
+  c.pipe = KP > 64 ? 0 : (prec == NMF_PREC_FP32 ? 2 : 1);
   return c;
 }
 
-PassCfg cfg_split(int col_tiles, int RT, int KP, int req_split, int req_nw) {
+PassCfg cfg_split(int col_tiles, int RT, int KP, int prec, int req_split, int req_nw) {
   PassCfg c;
-  c.nw = req_nw > 0 ? req_nw : 4;
-  const int cap = SIMDS * occupancy_for(KP);
-  int S = req_split > 0 ? req_split : std::max(1, cap / std::max(1, col_tiles * c.nw));
+  c.nw = req_nw > 0 ? req_nw : (prec == NMF_PREC_FP32 || KP > 64 ? 4 : 2);
+  int S = req_split > 0 ? req_split : std::max(1, 256 / std::max(1, col_tiles));
   S = std::min(S, std::max(1, RT / c.nw));
   c.tiles_per_split = (RT + S - 1) / S;
   c.splits = (RT + c.tiles_per_split - 1) / c.tiles_per_split;
@@ -471,8 +477,10 @@ PassCfg cfg_split(int col_tiles, int RT, int KP, int req_split, int req_nw) {
 }
 
 // Times candidate launch shapes of one fused half-step on the staged data
-// (split mode into a scratch partial buffer, so nothing the iteration reads
-// is written) and returns the fastest; cached per key in the handle.
+// and returns the fastest; cached per key in the handle.  A pass that may be
+// split is timed in split mode, one that updates in place is timed in update
+// mode; either way every output goes to a scratch buffer, so nothing the
+// iteration reads is written.
 int autotune_pass(nmf_handle h, const std::string& key, int prec, int KP, const DualArgs& base,
                   int col_tiles, int RT, bool allow_split, hipStream_t s, PassCfg* out) {
   auto it = h->tuned.find(key);
@@ -490,7 +498,11 @@ int autotune_pass(nmf_handle h, const std::string& key, int prec, int KP, const 
   int rc;
   float* scratch = nullptr;
   const int max_split = split_opts.back();
-  if ((rc = ws(h, "tune.partial", (size_t)max_split * 2 * KP * base.C_pad, &scratch))) return rc;
+  const size_t plane = (size_t)KP * base.C_pad;
+  // update mode: new factor (KP x C) + two FP32 or four bf16 copies + J partials
+  const size_t need = allow_split ? (size_t)max_split * 2 * plane : 3 * plane + 2 * (size_t)col_tiles;
+  if ((rc = ws(h, "tune.partial", need, &scratch))) return rc;
+  const int mode = allow_split ? MODE_SPLIT : MODE_UPDATE;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -505,14 +517,25 @@ int autotune_pass(nmf_handle h, const std::string& key, int prec, int KP, const 
         const int S = (RT + tps - 1) / tps;
         if (tps < nw) continue;
         DualArgs a = base;
-        a.partial = scratch;
         a.tiles_per_split = tps;
-        a.Jpart = nullptr;
+        if (allow_split) {
+          a.partial = scratch;
+          a.Jpart = nullptr;
+        } else {
+          a.Rt_out = scratch;
+          a.RtT = scratch + plane;
+          a.Rtp = scratch + 2 * plane;
+          a.RtTh = (__bf16*)(scratch + plane);
+          a.RtTl = a.RtTh + plane;
+          a.Rtph = (__bf16*)(scratch + 2 * plane);
+          a.Rtpl = a.Rtph + plane;
+          a.Jpart = (double*)(scratch + 3 * plane);
+        }
         const int pp = pipe_for(KP, pipe);
-        hipError_t e = launch_dual(prec, KP, MODE_SPLIT, nw, pp, a, col_tiles, S, s);
+        hipError_t e = launch_dual(prec, KP, mode, nw, pp, a, col_tiles, S, s);
         if (e != hipSuccess) continue;
         HIP_TRY(hipEventRecord(e0, s));
-        for (int r = 0; r < 3; ++r) HIP_TRY(launch_dual(prec, KP, MODE_SPLIT, nw, pp, a, col_tiles, S, s));
+        for (int r = 0; r < 3; ++r) HIP_TRY(launch_dual(prec, KP, mode, nw, pp, a, col_tiles, S, s));
         HIP_TRY(hipEventRecord(e1, s));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -720,7 +743,7 @@ int nmf_objective(nmf_handle h, const float* V, const float* M, const float* W, 
   LAUNCH(NMF_K_OTHER, launch_factor_fill(fill_args(Hf, H, 1, 0, 1, k), s));
   DualArgs a = pass_args(D, Mw, n_pad / 32, p_pad, (int)p, Wf, Hf.t, k, 0.f);
   a.Jpart = part;
-  const PassCfg pc = cfg_whole(p_pad / 32, n_pad / 32, KP, 0);
+  const PassCfg pc = cfg_whole(p_pad / 32, n_pad / 32, KP, precision, 0);
   LAUNCH(NMF_K_OBJECTIVE, launch_dual(precision, KP, MODE_OBJ, pc.nw, pc.pipe, a, p_pad / 32, 1, s));
   LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, p_pad / 32, Jdev, nullptr, s));
   int st = 0;
@@ -759,9 +782,9 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
 
   const int n_pad = round_up(n, 32), p_pad = round_up(p, 32);
   const int ntile = n_pad / 32, ptile = p_pad / 32;
-  PassCfg ca = cfg_whole(ptile, ntile, KP, prm->waves);
-  PassCfg cb = cfg_split(ntile, ptile, KP, prm->split, prm->waves);
-  ca.pipe = cb.pipe = pipe_for(KP, prm->pipeline);
+  PassCfg ca = cfg_whole(ptile, ntile, KP, prec, prm->waves);
+  PassCfg cb = cfg_split(ntile, ptile, KP, prec, prm->split, prm->waves);
+  if (prm->pipeline > 0) ca.pipe = cb.pipe = pipe_for(KP, prm->pipeline);
 
   float *D, *Mw, *DT, *MwT, *partial;
   double *part, *Jhist, *sum_mv2;
@@ -983,8 +1006,8 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
   hipStream_t s = (hipStream_t)stream;
   const int f_pad = round_up(f, 32), p_pad = round_up(p, 32);
   const int ftile = f_pad / 32, ptile = p_pad / 32;
-  PassCfg cb = cfg_split(ftile, ptile, KP, prm->split, prm->waves);
-  cb.pipe = pipe_for(KP, prm->pipeline);
+  PassCfg cb = cfg_split(ftile, ptile, KP, prec, prm->split, prm->waves);
+  if (prm->pipeline > 0) cb.pipe = pipe_for(KP, prm->pipeline);
   float *DT, *MwT, *partial;
   double* part;
   int* stat;

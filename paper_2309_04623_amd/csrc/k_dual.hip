@@ -108,7 +108,7 @@ __device__ __forceinline__ void load_ops(Ops<PREC, KP>& o, const DualArgs& a, in
 }
 
 template <int PREC, int KP, int MODE, int NW, int PIPE>
-__global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
+__global__ __launch_bounds__(64 * NW, (KP <= 32 && PIPE <= 2) ? 2 : 1) void k_dual(DualArgs a) {
   static_assert(KP % 32 == 0, "KP must be a multiple of 32");
   constexpr int MT = KP / 32;  // 32-row tiles of the num/den outputs
   __shared__ float red[(NW > 1) ? (NW - 1) * 2 * 16 * 64 : 1];
@@ -117,9 +117,18 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 31;
   const int half = lane >> 5;
-  const int tc = blockIdx.x;
+  // Workgroups are handed to the 8 XCDs round-robin in launch order; renumber
+  // them so that each XCD runs one contiguous range of (split, tile) in
+  // split-major order, and the workgroups that read the same rows of the
+  // left factor share that XCD's L2 instead of each XCD fetching them.
+  const int nb = gridDim.x * gridDim.y;
+  const int lin = blockIdx.y * gridDim.x + blockIdx.x;
+  const int per = nb >> 3, rem = nb & 7, xcd = lin & 7;
+  const int lin2 = xcd * per + min(xcd, rem) + (lin >> 3);
+  const int bx = lin2 % gridDim.x, by = lin2 / gridDim.x;
+  const int tc = bx;
   const int c0 = tc * TILE;
-  const int t_begin = blockIdx.y * a.tiles_per_split;
+  const int t_begin = by * a.tiles_per_split;
   const int t_end = min(t_begin + a.tiles_per_split, a.RT);
 
   // ---- right-factor tile, resident for the whole block ------------------
@@ -333,12 +342,12 @@ __global__ __launch_bounds__(64 * NW) void k_dual(DualArgs a) {
       double s = 0.0;
 #pragma unroll
       for (int w = 0; w < NW; ++w) s += jred[w];
-      a.Jpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+      a.Jpart[lin2] = s;
     }
   }
   if constexpr (MODE == MODE_SPLIT) {
     if (wave != 0) return;
-    float* pn = a.partial + (int64_t)blockIdx.y * 2 * KP * a.C_pad;
+    float* pn = a.partial + (int64_t)by * 2 * KP * a.C_pad;
     float* pd = pn + (int64_t)KP * a.C_pad;
 #pragma unroll
     for (int t = 0; t < MT; ++t) {

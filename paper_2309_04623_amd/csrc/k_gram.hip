@@ -236,7 +236,39 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
     const int j = tid;
     const double bj = j < KP ? bsh[j] : 0.0;
     const f32x4* c4 = reinterpret_cast<const f32x4*>(csh);
-    if constexpr (KP <= 128) {
+    if constexpr (KP <= 64) {
+      // One wave iterates: lane j keeps row j of G in registers and the
+      // coefficients travel through LDS.  A wave's LDS accesses execute in
+      // program order, so each iteration's broadcast reads see the previous
+      // iteration's writes without a workgroup barrier; the other waves wait
+      // at the end-of-frame barrier.
+      if (wave == 0) {
+        float g[KP];
+#pragma unroll
+        for (int i = 0; i < KP; ++i) g[i] = (j < K && i < K) ? G[j * K + i] : 0.f;
+        float cj = j < KP ? csh[j] : 0.f;
+        for (int it = 0; it < a.iters; ++it) {
+          float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+#pragma unroll
+          for (int i4 = 0; i4 < KQ; ++i4) {
+            const f32x4 cv = c4[i4];
+            d0 = fmaf(cv[0], g[4 * i4 + 0], d0);
+            d1 = fmaf(cv[1], g[4 * i4 + 1], d1);
+            d2 = fmaf(cv[2], g[4 * i4 + 2], d2);
+            d3 = fmaf(cv[3], g[4 * i4 + 3], d3);
+          }
+          const float den = (d0 + d1) + (d2 + d3);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          if (j < K) {
+            cj = mu_apply_d(cj, bj, (double)den, a.eps);
+            csh[j] = cj;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+    } else if constexpr (KP <= 128) {
       float g[KP];
 #pragma unroll
       for (int i = 0; i < KP; ++i) g[i] = (j < K && i < K) ? G[j * K + i] : 0.f;
