@@ -71,7 +71,10 @@ enum nmf_flags {
   NMF_F_VALIDATE_DATA = 1,   /* check data/weights, return NMF_ERR_* on bad */
   NMF_F_CLIP_NEGATIVE = 2,   /* negative data under weight: treat as masked */
   NMF_F_NORMALIZE_H = 4,     /* unit-L2 basis rows after the build          */
-  NMF_F_BINARY_WEIGHTS = 8,  /* weights are 0/1 (enables bitmask storage)   */
+  NMF_F_BINARY_WEIGHTS = 8,  /* weights are a mask: every positive weight
+                                counts as 1; the staged weights are kept as
+                                one bit per element instead of an FP32 copy
+                                (basis build and direct projection)          */
   NMF_F_MASKED_GRAM = 16,    /* projection through per-frame Gram matrices  */
   NMF_F_WARM_START = 32,     /* reserved: learned warm start                */
   NMF_F_ASYNC = 64,          /* do not synchronise; report filled later     */

@@ -792,8 +792,15 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   Factor Wf, Hf;
   const size_t nel = (size_t)n_pad * p_pad;
   const int nblk = std::max(ntile * ptile, ptile);
-  if ((rc = ws(h, "D", nel, &D)) || (rc = ws(h, "Mw", nel, &Mw)) || (rc = ws(h, "DT", nel, &DT)) ||
-      (rc = ws(h, "MwT", nel, &MwT)) ||
+  const bool binary = (prm->flags & NMF_F_BINARY_WEIGHTS) != 0;
+  uint16_t *Bb = nullptr, *BbT = nullptr;
+  Mw = MwT = nullptr;
+  if (binary) {
+    if ((rc = ws(h, "B", nel / 16, &Bb)) || (rc = ws(h, "BT", nel / 16, &BbT))) return rc;
+  } else if ((rc = ws(h, "Mw", nel, &Mw)) || (rc = ws(h, "MwT", nel, &MwT))) {
+    return rc;
+  }
+  if ((rc = ws(h, "D", nel, &D)) || (rc = ws(h, "DT", nel, &DT)) ||
       (rc = ws(h, "partial", (size_t)cb.splits * 2 * KP * n_pad, &partial)) ||
       (rc = ws(h, "part", (size_t)nblk, &part)) || (rc = ws(h, "Jhist", (size_t)T + 2, &Jhist)) ||
       (rc = ws(h, "summv2", 1, &sum_mv2)) || (rc = ws(h, "stat", 1, &stat)) ||
@@ -808,7 +815,7 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   HIP_TRY(hipMemsetAsync(stat, 0, sizeof(int), s));
   LAUNCH(NMF_K_OTHER, launch_set_int(iter, 0, s));
   StageArgs sa{V, M, n, p, n_pad, p_pad, (prm->flags & NMF_F_CLIP_NEGATIVE) ? 1 : 0,
-               D, Mw, DT, MwT, stat, part};
+               D, Mw, DT, MwT, stat, part, binary ? 1 : 0, Bb, BbT};
   int sblocks = 0;
   LAUNCH(NMF_K_OTHER, launch_stage(sa, &sblocks, s));
   LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, sblocks, sum_mv2, nullptr, s));
@@ -824,6 +831,7 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
 
   // H-rule over V: one workgroup per 32-pixel tile, all images.
   DualArgs A = pass_args(D, Mw, ntile, p_pad, (int)p, Wf, Hf.t, K, eps);
+  A.Mb = Bb;
   A.Jpart = part;
   A.Rt_out = Hf.t;
   A.RtT = Hf.m;
@@ -834,6 +842,7 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   A.Rtpl = Hf.tpl;
   // W-rule over V^T: 32-image tiles x chunks of pixel tiles, then the finish.
   DualArgs B = pass_args(DT, MwT, ptile, n_pad, (int)n, Hf, Wf.t, K, eps);
+  B.Mb = BbT;
   B.tiles_per_split = cb.tiles_per_split;
   B.partial = partial;
   if (prm->flags & NMF_F_AUTOTUNE) {
@@ -1013,7 +1022,11 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
   int* stat;
   Factor Cf, Hf;
   const size_t nel = (size_t)f_pad * p_pad;
-  if ((rc = ws(h, "pDT", nel, &DT)) || (rc = ws(h, "pMwT", nel, &MwT)) ||
+  const bool binary = (prm->flags & NMF_F_BINARY_WEIGHTS) != 0;
+  uint16_t* BbT = nullptr;
+  MwT = nullptr;
+  if (binary ? (rc = ws(h, "pBT", nel / 16, &BbT)) : (rc = ws(h, "pMwT", nel, &MwT))) return rc;
+  if ((rc = ws(h, "pDT", nel, &DT)) ||
       (rc = ws(h, "ppartial", (size_t)cb.splits * 2 * KP * f_pad, &partial)) ||
       (rc = ws(h, "ppart", (size_t)ftile * ptile, &part)) ||
       (rc = ws(h, "stat", 1, &stat)) || (rc = factor_alloc(h, "C", (int)f, f_pad, KP, &Cf)) ||
@@ -1022,7 +1035,7 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
   HIP_TRY(hipEventRecord(h->ev0, s));
   HIP_TRY(hipMemsetAsync(stat, 0, sizeof(int), s));
   StageArgs sa{T, M_T, f, p, f_pad, p_pad, (prm->flags & NMF_F_CLIP_NEGATIVE) ? 1 : 0,
-               nullptr, nullptr, DT, MwT, stat, part};
+               nullptr, nullptr, DT, MwT, stat, part, binary ? 1 : 0, nullptr, BbT};
   int sblocks = 0;
   LAUNCH(NMF_K_OTHER, launch_stage(sa, &sblocks, s));
   LAUNCH(NMF_K_OTHER, launch_factor_fill(fill_args(Hf, H, 1, 0, 1, K), s));
@@ -1034,6 +1047,7 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
     if ((rc = status_from_stage(st))) return rc;
   }
   DualArgs B = pass_args(DT, MwT, ptile, f_pad, (int)f, Hf, Cf.t, K, prm->floor_eps);
+  B.Mb = BbT;
   B.tiles_per_split = cb.tiles_per_split;
   B.partial = partial;
   FinishArgs F = finish_args(partial, cb.splits, Cf, (int)f, K, prm->floor_eps, prec);

@@ -29,6 +29,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a) {
         bad |= 4;
         m = 0.f;
       }
+      if (a.binary) m = m > 0.f ? 1.f : 0.f;
       if (m > 0.f) {
         if (!isfinite(v)) {
           bad |= 1;
@@ -63,12 +64,26 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a) {
     const int tr = acc_row(i, ln >> 5), tcol = ln & 31;
     if (a.D) {
       a.D[tileA + o] = tv[tr][tcol];
-      a.Mw[tileA + o] = tm[tr][tcol];
+      if (!a.binary) a.Mw[tileA + o] = tm[tr][tcol];
     }
     if (a.DT) {
       a.DT[tileB + o] = tv[tcol][tr];
-      a.MwT[tileB + o] = tm[tcol][tr];
+      if (!a.binary) a.MwT[tileB + o] = tm[tcol][tr];
     }
+  }
+  // Binary weights: lane ln of a tile keeps bit i for its register i.
+  if (a.binary && threadIdx.x < 128) {
+    const int ln = threadIdx.x & 63, half = ln >> 5, c = ln & 31;
+    const bool tr_side = threadIdx.x >= 64;
+    uint32_t bits = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = acc_row(i, half);
+      const float m = tr_side ? tm[c][r] : tm[r][c];
+      bits |= (m > 0.f ? 1u : 0u) << i;
+    }
+    if (!tr_side && a.D) a.B[(tileA >> 4) + ln] = (uint16_t)bits;
+    if (tr_side && a.DT) a.BT[(tileB >> 4) + ln] = (uint16_t)bits;
   }
   red[threadIdx.x] = acc;
   __syncthreads();

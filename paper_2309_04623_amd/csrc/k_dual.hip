@@ -45,6 +45,25 @@ __device__ __forceinline__ void load_tile(const float* p, f32x4 (&v)[4]) {
   for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(q + 64 * u);
 }
 
+// Weights of one tile as a wave holds them: FP32 values (16 per lane, loaded
+// like the data) or, for binary weights, one 16-bit mask per lane.
+template <bool BIN>
+struct MaskTile {
+  f32x4 v[4];
+  __device__ __forceinline__ void load(const float* pw, const uint16_t*, int64_t t) {
+    load_tile(pw + t * 1024, v);
+  }
+  __device__ __forceinline__ float get(int i) const { return v[i >> 2][i & 3]; }
+};
+template <>
+struct MaskTile<true> {
+  uint32_t b;
+  __device__ __forceinline__ void load(const float*, const uint16_t* pb, int64_t t) {
+    b = __builtin_nontemporal_load(pb + t * 64);
+  }
+  __device__ __forceinline__ float get(int i) const { return (b >> i) & 1u ? 1.f : 0.f; }
+};
+
 // Operand registers of one 32-row tile: the L rows (A operand of Y = L Rt)
 // and the permuted L^T block (A operand of num/den).
 template <int PREC, int KP>
@@ -107,7 +126,7 @@ __device__ __forceinline__ void load_ops(Ops<PREC, KP>& o, const DualArgs& a, in
   for (int t = 0; t < KP / 32; ++t) load_lt_tile<PREC, KP>(o, a, r0, lane, t);
 }
 
-template <int PREC, int KP, int MODE, int NW, int PIPE>
+template <int PREC, int KP, int MODE, int NW, int PIPE, bool BIN>
 __global__ __launch_bounds__(64 * NW, (KP <= 32 && PIPE <= 2) ? 2 : 1) void k_dual(DualArgs a) {
   static_assert(KP % 32 == 0, "KP must be a multiple of 32");
   constexpr int MT = KP / 32;  // 32-row tiles of the num/den outputs
@@ -166,7 +185,9 @@ __global__ __launch_bounds__(64 * NW, (KP <= 32 && PIPE <= 2) ? 2 : 1) void k_du
 
   const int64_t tile_base = (int64_t)tc * a.RT;
   const float* dcol = a.D + tile_base * 1024 + lane * 4;
-  const float* mcol = a.Mw + tile_base * 1024 + lane * 4;
+  const float* mcol = BIN ? nullptr : a.Mw + tile_base * 1024 + lane * 4;
+  const uint16_t* bcol = BIN ? a.Mb + tile_base * 64 + lane : nullptr;
+  using MK = MaskTile<BIN>;
   // PIPE 0: operands loaded at their use (large KP); PIPE 1: all operands of
   // a tile loaded at its start; PIPE 2: operands and data of the wave's next
   // tile loaded one tile ahead, so every wait covers loads issued a full
@@ -177,8 +198,8 @@ __global__ __launch_bounds__(64 * NW, (KP <= 32 && PIPE <= 2) ? 2 : 1) void k_du
 
   // One tile: consume (dv, mv, oc); prefetch the wave's next tile's data into
   // (dn, mn) and, with PIPE 2, its operands into on.
-  auto step = [&](const int tr, const f32x4 (&dv)[4], const f32x4 (&mv)[4], O& oc, f32x4 (&dn)[4],
-                  f32x4 (&mn)[4], O& on) {
+  auto step = [&](const int tr, const f32x4 (&dv)[4], const MK& mv, O& oc, f32x4 (&dn)[4], MK& mn,
+                  O& on) {
     const int r0 = tr * TILE;
     // Unconditional (past the end a step re-reads its own tile) so that the
     // number of loads in flight is static and the waits below stay precise.
@@ -191,7 +212,7 @@ __global__ __launch_bounds__(64 * NW, (KP <= 32 && PIPE <= 2) ? 2 : 1) void k_du
     }
     __builtin_amdgcn_sched_barrier(0);
     load_tile(dcol + (int64_t)trd * 1024, dn);
-    load_tile(mcol + (int64_t)trd * 1024, mn);
+    mn.load(mcol, bcol, trd);
     __builtin_amdgcn_sched_barrier(0);
 
     // ---- Y = L[r0:r0+32, :] * Rt ------------------------------------------
@@ -216,8 +237,9 @@ __global__ __launch_bounds__(64 * NW, (KP <= 32 && PIPE <= 2) ? 2 : 1) void k_du
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const float d = dv[i >> 2][i & 3];
-      const float m = mv[i >> 2][i & 3];
-      av[i] = m * d;
+      const float m = mv.get(i);
+      // binary weights: the staged data is already 0 where the weight is
+      av[i] = BIN ? d : m * d;
       zv[i] = m * y[i];
       if constexpr (MODE != MODE_SPLIT) {
         const float r = d - y[i];
@@ -268,12 +290,13 @@ __global__ __launch_bounds__(64 * NW, (KP <= 32 && PIPE <= 2) ? 2 : 1) void k_du
 
   int tr = t_begin + wave;
   if constexpr (PFD == 1) {
-    f32x4 dA[4], mA[4], dB[4], mB[4];
+    f32x4 dA[4], dB[4];
+    MK mA, mB;
     O oA, oB;
     if (tr < t_end) {
       if constexpr (PIPE >= 2) ops_for(oA, tr * TILE);
       load_tile(dcol + (int64_t)tr * 1024, dA);
-      load_tile(mcol + (int64_t)tr * 1024, mA);
+      mA.load(mcol, bcol, tr);
     }
     for (; tr < t_end; tr += 2 * NW) {
       step(tr, dA, mA, oA, dB, mB, oB);
@@ -282,15 +305,16 @@ __global__ __launch_bounds__(64 * NW, (KP <= 32 && PIPE <= 2) ? 2 : 1) void k_du
     }
   } else {
     // data two tiles ahead: three data buffers, two operand sets
-    f32x4 dA[4], mA[4], dB[4], mB[4], dC[4], mC[4];
+    f32x4 dA[4], dB[4], dC[4];
+    MK mA, mB, mC;
     O oA, oB;
     if (tr < t_end) {
       ops_for(oA, tr * TILE);
       load_tile(dcol + (int64_t)tr * 1024, dA);
-      load_tile(mcol + (int64_t)tr * 1024, mA);
+      mA.load(mcol, bcol, tr);
       const int t1 = (tr + NW < t_end) ? tr + NW : tr;
       load_tile(dcol + (int64_t)t1 * 1024, dB);
-      load_tile(mcol + (int64_t)t1 * 1024, mB);
+      mB.load(mcol, bcol, t1);
     }
     for (; tr < t_end; tr += 6 * NW) {
       step(tr, dA, mA, oA, dC, mC, oB);
@@ -420,15 +444,21 @@ __global__ __launch_bounds__(64 * NW, (KP <= 32 && PIPE <= 2) ? 2 : 1) void k_du
   }
 }
 
-template <int PREC, int KP, int MODE, int PIPE>
-static hipError_t launch_nw(int nw, const DualArgs& a, dim3 g, hipStream_t s) {
+template <int PREC, int KP, int MODE, int PIPE, bool BIN>
+static hipError_t launch_bin(int nw, const DualArgs& a, dim3 g, hipStream_t s) {
   switch (nw) {
-    case 1: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 1, PIPE>), g, dim3(64), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 2, PIPE>), g, dim3(128), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 4, PIPE>), g, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 1, PIPE, BIN>), g, dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 2, PIPE, BIN>), g, dim3(128), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_dual<PREC, KP, MODE, 4, PIPE, BIN>), g, dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int PREC, int KP, int MODE, int PIPE>
+static hipError_t launch_nw(int nw, const DualArgs& a, dim3 g, hipStream_t s) {
+  return a.Mb ? launch_bin<PREC, KP, MODE, PIPE, true>(nw, a, g, s)
+              : launch_bin<PREC, KP, MODE, PIPE, false>(nw, a, g, s);
 }
 
 template <int PREC, int KP, int MODE>

@@ -22,6 +22,9 @@ namespace nmf {
 struct DualArgs {
   const float* D;
   const float* Mw;
+  // binary weights instead of Mw (nullable): per tile 64 x 16 bits, lane l's
+  // bit i is the weight of its register i (same placement as the tile slots)
+  const uint16_t* Mb;
   int RT;               // row tiles (R_pad / 32)
   int tiles_per_split;  // row tiles per grid-y chunk
   int C_pad, C_valid;
@@ -127,6 +130,10 @@ struct StageArgs {
   float* MwT;
   int* status; // bit 0: non-finite data, bit 1: negative data, bit 2: bad weight
   double* part;
+  // binary weights: weight = (M > 0); bit tiles written instead of Mw / MwT
+  int binary;
+  uint16_t* B;   // bits of the D tiles (with D)
+  uint16_t* BT;  // bits of the DT tiles (with DT)
 };
 hipError_t launch_stage(const StageArgs& a, int* nblocks_out, hipStream_t s);
 

@@ -23,12 +23,13 @@ pytestmark = pytest.mark.gpu
 TOL = {"fp32": (1e-5, 1e-4), "bf16x3": (1e-4, 1e-3)}
 
 
-def _check_run(V, M, k, iters, precision, seed=7, tag=""):
+def _check_run(V, M, k, iters, precision, seed=7, tag="", flags=0):
     n, p = V.shape
     W0 = prng.init_matrix(seed, prng.MAT_W, n, k)
     H0 = prng.init_matrix(seed, prng.MAT_H, k, p)
     say(tag, f"n={n} p={p} k={k} iters={iters} prec={precision}")
-    Wg, Hg, Jg, rep = nmf.build_basis(dev(V), dev(M), k, iters, precision=precision, seed=seed)
+    Wg, Hg, Jg, rep = nmf.build_basis(dev(V), dev(M), k, iters, precision=precision, seed=seed,
+                                      flags=flags)
     Wg, Hg = host(Wg), host(Hg)
     Wo, Ho, Jo = nmf64.build_basis(V, M, W0, H0, iters)
     Jgpu64 = objective64(V, M, Wg, Hg)
@@ -97,6 +98,37 @@ def test_binary_weights_parity():
     lib = synth.make_cfg3(n=96, ny=40, nx=48, k0=20, frames=1)
     _check_run(lib.V, lib.M, 16, 60, "fp32", tag="cfg3-reduced")
     _check_run(lib.V, lib.M, 16, 60, "bf16x3", tag="cfg3-reduced")
+    _check_run(lib.V, lib.M, 16, 60, "fp32", tag="cfg3-reduced bitmask",
+               flags=nmf.F_BINARY_WEIGHTS)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("n,ny,nx,k", [(96, 40, 48, 16), (120, 25, 40, 100), (40, 9, 37, 40)])
+def test_binary_weight_bitmask_bitwise(precision, n, ny, nx, k):
+    """Binary weights stored as bitmasks (4 B + 1 bit per element instead of
+    8 B) give bit-identical factors and objective history to the same 0/1
+    weights stored as floats; any positive weight counts as 1."""
+    lib = synth.make_cfg3(n=n, ny=ny, nx=nx, k0=min(k + 4, n), frames=1)
+    V, M = lib.V, lib.M
+    say("bitmask", precision, n, ny * nx, k)
+    W1, H1, J1, r1 = nmf.build_basis(dev(V), dev(M), k, 25, precision=precision, seed=4)
+    W2, H2, J2, r2 = nmf.build_basis(dev(V), dev(M), k, 25, precision=precision, seed=4,
+                                     flags=nmf.F_BINARY_WEIGHTS)
+    assert np.array_equal(host(W1), host(W2)) and np.array_equal(host(H1), host(H2))
+    assert np.array_equal(J1, J2)
+    M3 = M * np.random.default_rng(1).uniform(0.5, 3.0, M.shape).astype(np.float32)
+    W3, H3, J3, _ = nmf.build_basis(dev(V), dev(M3), k, 25, precision=precision, seed=4,
+                                    flags=nmf.F_BINARY_WEIGHTS)
+    assert np.array_equal(host(W1), host(W3)) and np.array_equal(host(H1), host(H3))
+
+
+def test_binary_weight_bitmask_projection_bitwise():
+    lib = synth.make_cfg3(n=64, ny=40, nx=50, k0=12, frames=37)
+    H = np.abs(lib.H0[:10]).astype(np.float32)
+    say("bitmask projection")
+    C1, _ = nmf.project(dev(H), dev(lib.T), dev(lib.MT), 200, seed=5)
+    C2, _ = nmf.project(dev(H), dev(lib.T), dev(lib.MT), 200, seed=5, flags=nmf.F_BINARY_WEIGHTS)
+    assert np.array_equal(host(C1), host(C2))
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
