@@ -76,7 +76,11 @@ enum nmf_flags {
                                 one bit per element instead of an FP32 copy
                                 (basis build and direct projection)          */
   NMF_F_MASKED_GRAM = 16,    /* projection through per-frame Gram matrices  */
-  NMF_F_WARM_START = 32,     /* reserved: learned warm start                */
+  NMF_F_WARM_START = 32,     /* C_init is a warm start (e.g. from
+                                nmf_warmstart_infer): masked-Gram projection
+                                keeps it per frame only if its objective is
+                                not above the seeded cold start's, else it
+                                starts that frame cold (the fallback)        */
   NMF_F_ASYNC = 64,          /* do not synchronise; report filled later     */
   NMF_F_AUTOTUNE = 128       /* time candidate launch shapes of the fused
                                 passes on first use of a shape and cache the
@@ -178,7 +182,11 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
  * c_f G_f, G_f = H diag(m_f) H^T (same value in exact arithmetic).
  *   H       : k x p basis;  T, M_T : f x p frames and weights
  *   C_out   : f x k coefficients
- *   obj_out : nullable f doubles (device): final per-frame Eq. 2 cost     */
+ *   obj_out : nullable f doubles (device): final per-frame Eq. 2 cost
+ * NMF_F_WARM_START (masked-Gram form only, C_init required): per frame, the
+ * start with the lower objective of C_init and the seeded cold start is
+ * used; rep->status_flags gets bit NMF_RS_WARM_FALLBACK when any frame fell
+ * back, and nmf_warm_fallbacks() returns how many did.                    */
 int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float* T,
                 const float* M_T, int64_t f, const nmf_params* prm, const float* C_init,
                 float* C_out, double* obj_out, nmf_report* rep, void* stream);
@@ -200,6 +208,14 @@ int nmf_project_ragged(nmf_handle h, const float* H, int64_t k, int64_t p, int64
                        const float* val, const float* wt, const nmf_params* prm,
                        const float* C_init, float* C_out, uint64_t* frame_ticks,
                        nmf_report* rep, void* stream);
+
+/* Bit of nmf_report.status_flags: a warm-started projection fell back to
+ * the cold start for at least one frame. */
+#define NMF_RS_WARM_FALLBACK (1 << 8)
+
+/* Frames of the last synchronous warm-started projection on h that fell back
+ * to the cold start (-1 if none ran). */
+int64_t nmf_warm_fallbacks(nmf_handle h);
 
 /* Frequency (kHz) of the device clock used by frame_ticks. */
 double nmf_device_clock_khz(nmf_handle h);

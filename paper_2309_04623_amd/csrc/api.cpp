@@ -60,6 +60,7 @@ struct nmf_handle_s {
     float us;
   };
   std::unordered_map<std::string, Tuned> tuned;
+  int64_t last_fallbacks = -1;  // frames of the last warm start that fell back
 };
 
 namespace {
@@ -638,6 +639,10 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
     return rc;
   const bool sorted = ragged && c.f <= MAX_SORT_FRAMES && c.f > 1;
   if (sorted && (rc = ws(h, "gorder", (size_t)c.f, &order))) return rc;
+  const bool warm = (c.prm->flags & NMF_F_WARM_START) != 0;
+  if (warm && !c.C_init) return fail(NMF_ERR_ARG, "NMF_F_WARM_START needs C_init");
+  int* fb = nullptr;
+  if (warm && (rc = ws(h, "gfallback", (size_t)c.f, &fb))) return rc;
   GramArgs a{};
   a.HT = Hf.m;
   a.K = K;
@@ -660,6 +665,8 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   a.queue = queue;
   a.status = stat;
   a.ticks = c.ticks;
+  a.warm = warm ? 1 : 0;
+  a.fallback = fb;
   const FactorFillArgs fa = fill_args(Hf, c.H, 1, 0, 1, K);
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     hipError_t e;
@@ -678,7 +685,7 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
               (uint64_t)c.val, (uint64_t)c.wt, (uint64_t)c.C_init, (uint64_t)c.C_out,
               (uint64_t)c.ticks, (uint64_t)c.prm->seed, (uint64_t)c.prm->max_iter,
               (uint64_t)c.prm->flags, (uint64_t)__builtin_bit_cast(uint32_t, c.prm->floor_eps),
-              (uint64_t)Hf.m, (uint64_t)queue, (uint64_t)stat, (uint64_t)order});
+              (uint64_t)Hf.m, (uint64_t)queue, (uint64_t)stat, (uint64_t)order, (uint64_t)fb});
   HIP_TRY(hipEventRecord(h->ev0, s));
   HIP_TRY(run_graph(h, key, s, enqueue));
   HIP_TRY(hipEventRecord(h->ev1, s));
@@ -688,6 +695,13 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(prof_drain(h));
   if (st & 16) return fail(NMF_ERR_ARG, "CSR offsets or pixel indices out of range");
+  int64_t nfb = 0;
+  if (warm) {
+    std::vector<int> hfb((size_t)c.f);
+    HIP_TRY(hipMemcpy(hfb.data(), fb, (size_t)c.f * sizeof(int), hipMemcpyDeviceToHost));
+    for (int v : hfb) nfb += v;
+    h->last_fallbacks = nfb;
+  }
   if (c.prm->flags & NMF_F_VALIDATE_DATA) {
     if ((rc = status_from_stage(st))) return rc;
   } else if ((rc = status_from_stage(st & 4))) {
@@ -697,7 +711,7 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
     rep->iters_run = c.prm->max_iter;
-    rep->status_flags = 0;
+    rep->status_flags = nfb > 0 ? NMF_RS_WARM_FALLBACK : 0;
     rep->objective = 0.0;
     rep->objective_rel = 0.0;
     rep->elapsed_ms = ms;
@@ -1008,6 +1022,8 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
     HIP_TRY(prof_drain(h));
     return rc2;
   }
+  if (prm->flags & NMF_F_WARM_START)
+    return fail(NMF_ERR_UNSUPPORTED, "NMF_F_WARM_START needs the masked-Gram form");
   if (KP > KP_MAX) return fail(NMF_ERR_UNSUPPORTED, "k > 128 is not supported by this build");
   if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
   const int prec = prm->precision;
@@ -1118,6 +1134,8 @@ int nmf_project_ragged(nmf_handle h, const float* H, int64_t k, int64_t p, int64
   gc.ticks = frame_ticks;
   return project_gram(h, gc, (hipStream_t)stream, rep);
 }
+
+int64_t nmf_warm_fallbacks(nmf_handle h) { return h ? h->last_fallbacks : -1; }
 
 double nmf_device_clock_khz(nmf_handle h) {
   if (!h) return 0.0;

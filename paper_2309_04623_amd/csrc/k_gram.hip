@@ -45,6 +45,7 @@ template <int KP, bool RAGGED>
 __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   extern __shared__ __align__(16) float lds[];
   __shared__ int qslot;
+  __shared__ double wsel[2][gram_waves<KP>()];
   constexpr int NB = KP / 32;
   constexpr int NT = gram_tiles<KP>();
   constexpr int NWV = gram_waves<KP>();
@@ -230,6 +231,41 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       csh[tid] = c0;
     }
     __syncthreads();
+
+    if (a.warm) {
+      // Warm start with fallback: the supplied coefficients are kept only if
+      // their objective is not above that of the seeded cold start (the two
+      // are compared as c G c^T - 2 b c^T; the frame's constant cancels).
+      double qw = 0.0, qc = 0.0;
+      if (tid < K) {
+        double gw = 0.0, gc = 0.0;
+        for (int i = 0; i < K; ++i) {
+          const double g = G[tid * K + i];
+          gw += g * (double)csh[i];
+          gc += g * (double)sm_uniform(key, (uint64_t)f * K + i);
+        }
+        const double cw = csh[tid], cc = sm_uniform(key, (uint64_t)f * K + tid);
+        qw = cw * (gw - 2.0 * bsh[tid]);
+        qc = cc * (gc - 2.0 * bsh[tid]);
+      }
+      qw = wave_sum(qw);
+      qc = wave_sum(qc);
+      if (lane == 0) {
+        wsel[0][wave] = qw;
+        wsel[1][wave] = qc;
+      }
+      __syncthreads();
+      double sw = 0.0, sc = 0.0;
+#pragma unroll
+      for (int w = 0; w < NWV; ++w) {
+        sw += wsel[0][w];
+        sc += wsel[1][w];
+      }
+      const bool keep = sw <= sc;  // false for a non-finite warm objective
+      if (!keep && tid < K) csh[tid] = sm_uniform(key, (uint64_t)f * K + tid);
+      if (a.fallback && tid == 0) a.fallback[f] = keep ? 0 : 1;
+      __syncthreads();
+    }
 
     // ---- iterations: (c G)_j with row j of G in registers (K <= 128) or
     // read from LDS (consecutive j across lanes, conflict-free) ------------

@@ -181,6 +181,9 @@ struct GramArgs {
   int* queue;          // zeroed before the launch
   int* status;         // bits as staging, plus 16 = bad CSR entry
   uint64_t* ticks;     // nullable: 2 per frame
+  int warm;            // C_init is a warm start: fall back to the cold start
+                       // per frame when its objective is lower
+  int* fallback;       // nullable: per frame, 1 where the cold start was used
 };
 size_t gram_lds_bytes(int K, int KP);
 hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, hipStream_t s,

@@ -73,6 +73,7 @@ _SIGS = {
                                           ctypes.POINTER(Params), _vp, _vp, _vp,
                                           ctypes.POINTER(Report), _vp]),
     "nmf_device_clock_khz": (ctypes.c_double, [_vp]),
+    "nmf_warm_fallbacks": (ctypes.c_int64, [_vp]),
     "nmf_subtract": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp]),
     "nmf_warmstart_param_count": (ctypes.c_int64, [_i32]),
     "nmf_warmstart_init": (ctypes.c_int, [_vp, _vp, _i32, _u64, _vp]),
@@ -252,11 +253,14 @@ def build_basis(V, M, k, iters, *, precision="fp32", W_init=None, H_init=None, s
 
 
 def project(H, T, MT, iters, *, C_init=None, precision="fp32", seed=0, flags=0, eps=1e-30,
-            split=0, want_objective=False, gram=False, handle=None):
+            split=0, want_objective=False, gram=False, warm=False, handle=None):
     """Target modelling: per-frame coefficients with the basis fixed
-    (``gram=True``: through per-frame masked Gram matrices)."""
+    (``gram=True``: through per-frame masked Gram matrices; ``warm=True``:
+    C_init is a warm start with per-frame fallback to the cold start)."""
     if gram:
         flags |= F_MASKED_GRAM
+    if warm:
+        flags |= F_WARM_START
     torch = _torch()
     dev = H.device.index or 0
     h = handle or default_handle(dev)
@@ -305,9 +309,11 @@ def profile_get(handle: Handle, kernel_class: int):
 
 
 def project_ragged(H, offsets, pix, val, wt, iters, *, C_init=None, seed=0, flags=0, eps=1e-30,
-                   want_ticks=False, handle=None):
+                   want_ticks=False, warm=False, handle=None):
     """Projection of CSR frames (one persistent launch, masked Gram form).
     offsets: int64 (f+1), pix: int32, val/wt: float32 (wt may be None)."""
+    if warm:
+        flags |= F_WARM_START
     torch = _torch()
     dev = H.device.index or 0
     h = handle or default_handle(dev)
@@ -324,6 +330,13 @@ def project_ragged(H, offsets, pix, val, wt, iters, *, C_init=None, seed=0, flag
         _dev_ptr(wt, "wt", torch.float32), ctypes.byref(prm), _dev_ptr(C_init, "C_init", torch.float32),
         _dev_ptr(C, "C_out"), _dev_ptr(ticks, "frame_ticks"), ctypes.byref(rep), _stream(dev)))
     return (C, ticks, rep.as_dict()) if want_ticks else (C, rep.as_dict())
+
+
+def warm_fallbacks(handle=None, device=0) -> int:
+    """Frames of the last warm-started projection that fell back to the cold
+    start (-1 if none ran on the handle)."""
+    h = handle or default_handle(device)
+    return int(lib().nmf_warm_fallbacks(h.h))
 
 
 def device_clock_khz(handle=None, device=0) -> float:
