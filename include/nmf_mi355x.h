@@ -72,9 +72,10 @@ enum nmf_flags {
   NMF_F_CLIP_NEGATIVE = 2,   /* negative data under weight: treat as masked */
   NMF_F_NORMALIZE_H = 4,     /* unit-L2 basis rows after the build          */
   NMF_F_BINARY_WEIGHTS = 8,  /* weights are a mask: every positive weight
-                                counts as 1; the staged weights are kept as
-                                one bit per element instead of an FP32 copy
-                                (basis build and direct projection)          */
+                                counts as 1 (every call); the basis build and
+                                the direct projection keep the staged
+                                weights as one bit per element instead of an
+                                FP32 copy                                    */
   NMF_F_MASKED_GRAM = 16,    /* projection through per-frame Gram matrices  */
   NMF_F_WARM_START = 32,     /* C_init is a warm start (e.g. from
                                 nmf_warmstart_infer): masked-Gram projection
@@ -159,6 +160,14 @@ int nmf_objective(nmf_handle h, const float* V, const float* M, const float* W,
  * times from (W_init, H_init), or from the seeded U(0,1) init when those are
  * NULL.  After each update x := max(x, floor_eps); a zero denominator keeps
  * the factor.  Data under zero weight are ignored whatever their value.
+ * Stop rule (Sec. 2: iterate until the change reaches a set value or the
+ * cap), on when tol > 0 and check_every = c > 0: J[t] is the Eq. 2 cost of
+ * the iterate entering iteration t (known during that iteration's H-rule
+ * pass); at t = c, 2c, ... the device tests (J[t-c] - J[t]) / J[t-c] < tol
+ * and, when it passes, iteration t is the last one (rep->iters_run = t + 1).
+ * The test runs on the device; no host round trip decides it.  Without it
+ * by max_iter the call returns NMF_WARN_MAXITER.  With NMF_F_ASYNC and a
+ * stop rule, rep->iters_run is -1 (only the device knows it).
  *   V, M            : n x p inputs
  *   W_init, H_init  : nullable n x k and k x p starts
  *   W_out, H_out    : n x k and k x p results
@@ -194,7 +203,8 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
 /* Same iteration for frames stored as CSR rows, always through the masked
  * Gram form: frame i owns entries offsets[i] .. offsets[i+1]-1 of pix (int32
  * pixel index in [0, p)), val (float32 data) and wt (float32 weight; NULL =
- * all ones); pixels absent from a frame carry weight 0.  Pixel indices
+ * all ones, as is NMF_F_BINARY_WEIGHTS); pixels absent from a frame carry
+ * weight 0.  Pixel indices
  * within a frame must be distinct.  offsets: f + 1 int64 (device) with
  * 0 <= offsets[i] <= offsets[i+1] <= nnz; entries that break this, or a
  * pixel index outside [0, p), are skipped and reported as NMF_ERR_ARG.

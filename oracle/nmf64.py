@@ -123,6 +123,42 @@ def build_basis(V, M, W0, H0, iters, eps=EPS_FLOOR, normalize=False, history=Tru
     return W, H, J
 
 
+def stop_test(J, t, check_every, tol):
+    """Stopping rule (Sec. 2, after Eq. 3: iterate until the change reaches a
+    set value or the iteration cap).  The quantity is not defined in the
+    paper; the reading here is the relative decrease of the Eq. 2 cost over
+    the last ``check_every`` iterations, tested when t is a positive multiple
+    of ``check_every``:  (J[t - c] - J[t]) / J[t - c] < tol."""
+    c = int(check_every)
+    if c <= 0 or t < c or t % c:
+        return False
+    j0 = J[t - c]
+    return bool(j0 > 0 and (j0 - J[t]) / j0 < tol)
+
+
+def build_basis_tol(V, M, W0, H0, max_iter, check_every, tol, eps=EPS_FLOOR):
+    """Basis construction with the stopping rule of ``stop_test``.  J[t] is
+    the cost of the iterate entering iteration t; iteration t is carried out
+    in full (H-rule, then W-rule) and, if the rule passes at t, it is the
+    last one.  Returns (W, H, J, iterations run) with J[0..run]."""
+    Vh, Mw, status = prep(V, M)
+    if status:
+        raise ValueError(f"unusable data: {status}")
+    W = _f64(W0).copy()
+    H = _f64(H0).copy()
+    J = []
+    run = 0
+    for t in range(max_iter):
+        J.append(objective(Vh, Mw, W, H))
+        H = update_H(Vh, Mw, W, H, eps)
+        W = update_W(Vh, Mw, W, H, eps)
+        run = t + 1
+        if stop_test(J, t, check_every, tol):
+            break
+    J.append(objective(Vh, Mw, W, H))
+    return W, H, np.array(J), run
+
+
 def normalize_components(W, H):
     """Rescale each component to unit L2 norm, moving the scale into W, so
     W H is unchanged (the paper is silent; optional post-processing)."""

@@ -661,6 +661,7 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   a.iters = c.prm->max_iter;
   a.eps = c.prm->floor_eps;
   a.clip_negative = (c.prm->flags & NMF_F_CLIP_NEGATIVE) ? 1 : 0;
+  a.binary = (c.prm->flags & NMF_F_BINARY_WEIGHTS) ? 1 : 0;
   a.C_out = c.C_out;
   a.queue = queue;
   a.status = stat;
@@ -818,16 +819,20 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
       (rc = ws(h, "partial", (size_t)cb.splits * 2 * KP * n_pad, &partial)) ||
       (rc = ws(h, "part", (size_t)nblk, &part)) || (rc = ws(h, "Jhist", (size_t)T + 2, &Jhist)) ||
       (rc = ws(h, "summv2", 1, &sum_mv2)) || (rc = ws(h, "stat", 1, &stat)) ||
-      (rc = ws(h, "iter", 1, &iter)) ||
+      (rc = ws(h, "iter", 4, &iter)) ||
       (rc = factor_alloc(h, "W", (int)n, n_pad, KP, &Wf)) ||
       (rc = factor_alloc(h, "H", (int)p, p_pad, KP, &Hf)))
     return rc;
   double* hostJ = nullptr;
-  if ((rc = pinned_get(h, (size_t)T + 2, &hostJ))) return rc;
+  if ((rc = pinned_get(h, (size_t)T + 3, &hostJ))) return rc;
 
+  // iter[0]: iterations done; iter[1]: stop requested by the stop test;
+  // iter[2]: stop seen by an update pass (see the kernels' stop flags)
+  int* stop_req = iter + 1;
+  int* stop_seen = iter + 2;
   HIP_TRY(hipEventRecord(h->ev0, s));
   HIP_TRY(hipMemsetAsync(stat, 0, sizeof(int), s));
-  LAUNCH(NMF_K_OTHER, launch_set_int(iter, 0, s));
+  HIP_TRY(hipMemsetAsync(iter, 0, 4 * sizeof(int), s));
   StageArgs sa{V, M, n, p, n_pad, p_pad, (prm->flags & NMF_F_CLIP_NEGATIVE) ? 1 : 0,
                D, Mw, DT, MwT, stat, part, binary ? 1 : 0, Bb, BbT};
   int sblocks = 0;
@@ -875,11 +880,24 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   F.iter = iter;
   F.status = stat;
 
+  // Stop rule (Sec. 2: iterate until the change reaches a set value or the
+  // iteration cap): evaluated on the device by the finish kernel from the
+  // objective history, so no host round trip decides it; once it passes,
+  // the remaining launches return at once.
   const int c = (prm->tol > 0.0 && prm->check_every > 0) ? prm->check_every : 0;
+  if (c) {
+    F.check_every = c;
+    F.tol = prm->tol;
+    F.stop_req = stop_req;
+    F.stop_seen = stop_seen;
+    A.stop_req = stop_req;
+    A.stop_seen = stop_seen;
+    B.stop_req = stop_req;
+  }
   // Iterations run as replays of a captured graph of ``chunk`` iterations
   // (the finish kernel advances the device iteration counter, so every
   // chunk is the same launch sequence).
-  const int chunk = c ? c : std::min(T, 64);
+  const int chunk = c ? std::max(c, std::min(T, 64) / c * c) : std::min(T, 64);
   auto enqueue_iters = [&](hipStream_t s, int count) -> hipError_t {
     hipError_t e;
     for (int i = 0; i < count; ++i) {
@@ -894,68 +912,85 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
     }
     return hipSuccess;
   };
+  // Every value baked into the captured launches is part of the key: buffer
+  // addresses (they move when the workspace grows), the weight storage, the
+  // launch shapes and the stop rule.
   auto iter_key = [&](int count) {
-    return key_of("iters", {(uint64_t)D, (uint64_t)DT, (uint64_t)Wf.m, (uint64_t)Hf.m,
-                            (uint64_t)partial, (uint64_t)part, (uint64_t)Jhist, (uint64_t)iter,
-                            (uint64_t)stat, (uint64_t)n, (uint64_t)p, (uint64_t)K,
-                            (uint64_t)prec, (uint64_t)__builtin_bit_cast(uint32_t, eps),
-                            (uint64_t)ca.nw, (uint64_t)cb.nw, (uint64_t)cb.splits,
-                            (uint64_t)count});
+    return key_of("iters",
+                  {(uint64_t)D, (uint64_t)DT, (uint64_t)Mw, (uint64_t)MwT, (uint64_t)Bb,
+                   (uint64_t)BbT, (uint64_t)Wf.m, (uint64_t)Wf.mh, (uint64_t)Wf.ml,
+                   (uint64_t)Wf.t, (uint64_t)Wf.tp, (uint64_t)Wf.tph, (uint64_t)Wf.tpl,
+                   (uint64_t)Hf.m, (uint64_t)Hf.mh, (uint64_t)Hf.ml, (uint64_t)Hf.t,
+                   (uint64_t)Hf.tp, (uint64_t)Hf.tph, (uint64_t)Hf.tpl, (uint64_t)partial,
+                   (uint64_t)part, (uint64_t)Jhist, (uint64_t)iter, (uint64_t)stat, (uint64_t)n,
+                   (uint64_t)p, (uint64_t)K, (uint64_t)prec, (uint64_t)binary,
+                   (uint64_t)__builtin_bit_cast(uint32_t, eps), (uint64_t)ca.nw, (uint64_t)ca.pipe,
+                   (uint64_t)ca.tiles_per_split, (uint64_t)cb.nw, (uint64_t)cb.pipe,
+                   (uint64_t)cb.splits, (uint64_t)cb.tiles_per_split, (uint64_t)c,
+                   __builtin_bit_cast(uint64_t, c ? prm->tol : 0.0), (uint64_t)count});
   };
+  // The device decides the stop; the host only stops enqueueing chunks once
+  // it has seen the flag.  After each chunk the flag is copied to pinned
+  // memory, and the copy of the previous chunk is read only after the next
+  // chunk is queued, so the device never idles waiting for the host.
   int t = 0;
-  bool stopped = false;
-  int pending_check = -1;  // iteration whose J copy is in flight
-  hipEvent_t chk = nullptr;
-  if (c) HIP_TRY(hipEventCreateWithFlags(&chk, hipEventDisableTiming));
+  int* host_flags = reinterpret_cast<int*>(hostJ + T + 1);  // two ints after J
+  hipEvent_t chk[2] = {nullptr, nullptr};
+  int inflight = -1, slot = 0;
+  if (c) {
+    HIP_TRY(hipEventCreateWithFlags(&chk[0], hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&chk[1], hipEventDisableTiming));
+    host_flags[0] = host_flags[1] = 0;
+  }
+  hipError_t loop_err = hipSuccess;
   while (t < T) {
     const int count = std::min(chunk, T - t);
-    HIP_TRY(run_graph(h, iter_key(count), s, [&](hipStream_t st) { return enqueue_iters(st, count); }));
+    loop_err = run_graph(h, iter_key(count), s, [&](hipStream_t st) { return enqueue_iters(st, count); });
+    if (loop_err != hipSuccess) break;
     t += count;
     if (!c) continue;
-    // J of the last iteration of a chunk is known once that chunk completes;
-    // decide on the previous chunk's value so that one chunk stays queued.
-    if (pending_check >= 0) {
-      HIP_TRY(hipEventSynchronize(chk));
-      const int t1 = pending_check;
-      if (t1 >= c) {
-        const double j0 = hostJ[t1 - c], j1 = hostJ[t1];
-        if (!std::isfinite(j1)) break;
-        if (j0 > 0 && (j0 - j1) / j0 < prm->tol) {
-          stopped = true;
-          break;
-        }
-      }
+    if ((loop_err = hipMemcpyAsync(host_flags + slot, stop_req, sizeof(int),
+                                   hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (loop_err = hipEventRecord(chk[slot], s)) != hipSuccess)
+      break;
+    if (inflight >= 0) {
+      if ((loop_err = hipEventSynchronize(chk[inflight])) != hipSuccess) break;
+      if (host_flags[inflight]) break;  // stopped during an earlier chunk
     }
-    HIP_TRY(hipMemcpyAsync(hostJ + (t - 1), Jhist + (t - 1), sizeof(double),
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipEventRecord(chk, s));
-    pending_check = t - 1;
+    inflight = slot;
+    slot ^= 1;
   }
-  if (chk) {
-    (void)hipEventSynchronize(chk);
-    (void)hipEventDestroy(chk);
+  for (hipEvent_t e : chk) {
+    if (!e) continue;
+    (void)hipEventSynchronize(e);
+    (void)hipEventDestroy(e);
   }
-  const int iters_run = t;
-  // Objective after the last iteration.
+  HIP_TRY(loop_err);
+  // Objective after the last iteration, stored at Jhist[iterations done].
   LAUNCH(NMF_K_OBJECTIVE, launch_dual(prec, KP, MODE_OBJ, ca.nw, ca.pipe, A, ptile, 1, s));
-  LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, ptile, Jhist + iters_run, stat, s));
+  LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, ptile, Jhist, stat, s, iter));
   if (prm->flags & NMF_F_NORMALIZE_H) LAUNCH(NMF_K_OTHER, launch_normalize(Hf.t, KP, p_pad, K, Wf.t, n_pad, s));
   LAUNCH(NMF_K_OTHER, launch_factor_out(Wf.t, (int)n, n_pad, K, KP, 0, W_out, s));
   LAUNCH(NMF_K_OTHER, launch_factor_out(Hf.t, (int)p, p_pad, K, KP, 1, H_out, s));
   HIP_TRY(hipEventRecord(h->ev1, s));
   if (prm->flags & NMF_F_ASYNC) {
     if (rep) {
-      rep->iters_run = iters_run;
+      rep->iters_run = c ? -1 : t;  // with a stop rule only the device knows
       rep->status_flags = 0;
     }
     return NMF_OK;
   }
   int st = 0;
   double mv2 = 0.0;
+  int dev_flags[3] = {0, 0, 0};
   HIP_TRY(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(&mv2, sum_mv2, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(hostJ, Jhist, sizeof(double) * (iters_run + 1), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(dev_flags, iter, sizeof(dev_flags), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hostJ, Jhist, sizeof(double) * (T + 1), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  const int iters_run = dev_flags[0];
+  const bool stopped = dev_flags[1] != 0;
+  if (iters_run < 0 || iters_run > T) return fail(NMF_ERR_HIP, "iteration counter out of range");
   HIP_TRY(prof_drain(h));
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
@@ -1017,7 +1052,10 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
     if (rc2 < 0 || !obj_out) return rc2;
     DeviceGuard g(h->device);
     hipStream_t s = (hipStream_t)stream;
-    LAUNCH(NMF_K_OTHER, launch_frame_objective(H, C_out, T, M_T, f, K, p, obj_out, s));
+    LAUNCH(NMF_K_OTHER, launch_frame_objective(H, C_out, T, M_T, f, K, p,
+                                               (prm->flags & NMF_F_BINARY_WEIGHTS) ? 1 : 0,
+                                               (prm->flags & NMF_F_CLIP_NEGATIVE) ? 1 : 0,
+                                               obj_out, s));
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(prof_drain(h));
     return rc2;
@@ -1072,7 +1110,10 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
     LAUNCH(NMF_K_PROJECT, launch_finish(F, s));
   }
   LAUNCH(NMF_K_OTHER, launch_factor_out(Cf.t, (int)f, f_pad, K, KP, 0, C_out, s));
-  if (obj_out) LAUNCH(NMF_K_OTHER, launch_frame_objective(H, C_out, T, M_T, f, K, p, obj_out, s));
+  if (obj_out)
+    LAUNCH(NMF_K_OTHER, launch_frame_objective(H, C_out, T, M_T, f, K, p, binary ? 1 : 0,
+                                               (prm->flags & NMF_F_CLIP_NEGATIVE) ? 1 : 0,
+                                               obj_out, s));
   HIP_TRY(hipEventRecord(h->ev1, s));
   if (prm->flags & NMF_F_ASYNC) return NMF_OK;
   int st = 0;

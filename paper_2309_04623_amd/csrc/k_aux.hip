@@ -106,7 +106,7 @@ hipError_t launch_stage(const StageArgs& a, int* nblocks_out, hipStream_t s) {
 // Fixed-order FP64 reduction (single block)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_reduce_f64(const double* part, int n, double* out,
-                                                   int* status) {
+                                                   int* status, const int* out_index) {
   __shared__ double red[256];
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) s += part[i];
@@ -117,14 +117,14 @@ __global__ __launch_bounds__(256) void k_reduce_f64(const double* part, int n, d
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = red[0];
+    out[out_index ? *out_index : 0] = red[0];
     if (status && !isfinite(red[0])) atomicOr(status, 8);
   }
 }
 
-hipError_t launch_reduce_f64(const double* part, int n, double* out, int* status,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, s, part, n, out, status);
+hipError_t launch_reduce_f64(const double* part, int n, double* out, int* status, hipStream_t s,
+                             const int* out_index) {
+  hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, s, part, n, out, status, out_index);
   return hipGetLastError();
 }
 
@@ -206,6 +206,7 @@ hipError_t launch_factor_out(const float* t, int rows, int rows_pad, int K, int 
 // Block = 64 columns x 4 groups of splits.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_finish(FinishArgs a) {
+  if (a.stop_seen && *a.stop_seen) return;  // an earlier iteration was the last
   __shared__ double rn[4][64];
   __shared__ double rd[4][64];
   __shared__ double rj[256];
@@ -254,9 +255,18 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs a) {
     }
     if (threadIdx.x == 0) {
       const int t = *a.iter;
-      a.Jhist[t] = rj[0];
+      const double J = rj[0];
+      a.Jhist[t] = J;
       *a.iter = t + 1;
-      if (!isfinite(rj[0])) atomicOr(a.status, 8);
+      if (!isfinite(J)) atomicOr(a.status, 8);
+      // Stop rule on the relative decrease of the objective over the last
+      // check_every iterations; J is the cost of the iterate entering
+      // iteration t, so when it passes iteration t is the last one.
+      const int c = a.check_every;
+      if (a.stop_req && c > 0 && t >= c && t % c == 0) {
+        const double j0 = a.Jhist[t - c];
+        if (j0 > 0.0 && (j0 - J) / j0 < a.tol) *a.stop_req = 1;
+      }
     }
   }
 }
@@ -339,7 +349,8 @@ hipError_t launch_subtract(const float* H, const float* C, const float* T, const
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_frame_objective(const float* H, const float* C,
                                                         const float* T, const float* MT, int k,
-                                                        int64_t p, double* out) {
+                                                        int64_t p, int binary, int clip_negative,
+                                                        double* out) {
   extern __shared__ float cs[];
   __shared__ double red[256];
   const int64_t f = blockIdx.x;
@@ -347,11 +358,14 @@ __global__ __launch_bounds__(256) void k_frame_objective(const float* H, const f
   __syncthreads();
   double s = 0.0;
   for (int64_t j = threadIdx.x; j < p; j += 256) {
-    const float m = MT[f * p + j];
+    float m = MT[f * p + j];
+    if (binary) m = m > 0.f ? 1.f : 0.f;
+    const float t = T[f * p + j];
+    if (clip_negative && t < 0.f) m = 0.f;
     if (m > 0.f) {
       double acc = 0.0;
       for (int i = 0; i < k; ++i) acc = fma((double)cs[i], (double)H[(int64_t)i * p + j], acc);
-      const double d = (double)T[f * p + j] - acc;
+      const double d = (double)t - acc;
       s += (double)m * d * d;
     }
   }
@@ -365,10 +379,10 @@ __global__ __launch_bounds__(256) void k_frame_objective(const float* H, const f
 }
 
 hipError_t launch_frame_objective(const float* H, const float* C, const float* T,
-                                  const float* MT, int64_t f, int k, int64_t p, double* out,
-                                  hipStream_t s) {
+                                  const float* MT, int64_t f, int k, int64_t p, int binary,
+                                  int clip_negative, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_frame_objective, dim3((unsigned)f), dim3(256), k * sizeof(float), s, H, C,
-                     T, MT, k, p, out);
+                     T, MT, k, p, binary, clip_negative, out);
   return hipGetLastError();
 }
 

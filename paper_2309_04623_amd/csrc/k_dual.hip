@@ -130,6 +130,11 @@ template <int PREC, int KP, int MODE, int NW, int PIPE, bool BIN>
 __global__ __launch_bounds__(64 * NW, (KP <= 32 && PIPE <= 2) ? 2 : 1) void k_dual(DualArgs a) {
   static_assert(KP % 32 == 0, "KP must be a multiple of 32");
   constexpr int MT = KP / 32;  // 32-row tiles of the num/den outputs
+  if (MODE != MODE_OBJ && a.stop_req && *a.stop_req) {
+    // the stop test passed after an earlier iteration: nothing to do
+    if (a.stop_seen && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.stop_seen = 1;
+    return;
+  }
   __shared__ float red[(NW > 1) ? (NW - 1) * 2 * 16 * 64 : 1];
   __shared__ double jred[NW];
   const int wave = threadIdx.x >> 6;

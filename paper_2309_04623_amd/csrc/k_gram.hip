@@ -158,6 +158,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
             bad |= 4;
             m = 0.f;
           }
+          if (a.binary) m = m > 0.f ? 1.f : 0.f;
           if (m > 0.f) {
             if (!isfinite(t)) {
               bad |= 1;
@@ -226,8 +227,11 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
     if (tid < KP) {
       bsh[tid] = tid < K ? bacc : 0.0;
       float c0 = 0.f;
-      if (tid < K)
+      if (tid < K) {
         c0 = a.C_init ? a.C_init[(int64_t)f * K + tid] : sm_uniform(key, (uint64_t)f * K + tid);
+        // a warm start is clamped to the floor (a zero would never move)
+        if (a.warm) c0 = fmaxf(c0, a.eps);
+      }
       csh[tid] = c0;
     }
     __syncthreads();

@@ -53,6 +53,13 @@ struct DualArgs {
   __bf16* Rtpl;
   int K;
   float eps;
+  // on-device stop (nullable): a set *stop_req makes the launch return at
+  // once; the first block of an update-mode launch that sees it also sets
+  // *stop_seen, which the finish kernel reads (the finish launch that sets
+  // *stop_req must not read it, so the two flags trail each other by one
+  // launch)
+  const int* stop_req;
+  int* stop_seen;
 };
 
 enum DualMode { MODE_UPDATE = 0, MODE_SPLIT = 1, MODE_OBJ = 2 };
@@ -68,6 +75,9 @@ hipError_t launch_dual(int prec, int kp, int mode, int nw, int pipe, const DualA
 // the update to the factor (old value read from t, the KP x C_pad layout)
 // and refreshes every layout.  Optionally also sums the objective partials
 // of the preceding H-rule pass into Jhist[*iter] and advances *iter.
+// With a stop test (check_every > 0, tol > 0): at t = *iter, a multiple of
+// check_every and >= check_every, the iteration is the last one when
+// (Jhist[t - c] - Jhist[t]) / Jhist[t - c] < tol; *stop_req is then set.
 struct FinishArgs {
   const float* partial;  // [S][2][KP][C_pad]
   int S, KP, C_pad, C_valid, K;
@@ -85,6 +95,10 @@ struct FinishArgs {
   double* Jhist;
   int* iter;
   int* status;
+  int check_every;
+  double tol;
+  int* stop_req;         // nullable: set when the stop test passes
+  const int* stop_seen;  // nullable: when set, the launch returns at once
 };
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
 
@@ -137,9 +151,11 @@ struct StageArgs {
 };
 hipError_t launch_stage(const StageArgs& a, int* nblocks_out, hipStream_t s);
 
-// Fixed-order FP64 sum of ``n`` partials into out[0] (single block).
-// With ``check``: status |= 8 if the sum is not finite.
-hipError_t launch_reduce_f64(const double* part, int n, double* out, int* status, hipStream_t s);
+// Fixed-order FP64 sum of ``n`` partials into out[0], or out[*out_index]
+// when out_index is given (single block).  With ``status``: status |= 8 if
+// the sum is not finite.
+hipError_t launch_reduce_f64(const double* part, int n, double* out, int* status, hipStream_t s,
+                             const int* out_index = nullptr);
 
 hipError_t launch_init_uniform(uint64_t seed, int matrix_id, int64_t count, float* out,
                                hipStream_t s);
@@ -154,10 +170,12 @@ hipError_t launch_subtract(const float* H, const float* C, const float* T, const
                            int64_t f, int k, int64_t p, const float* scale, float* model,
                            float* resid, hipStream_t s);
 
-// Per-frame objective sum_p m (t - c H)^2 for dense frames.
+// Per-frame objective sum_p m (t - c H)^2 for dense frames, with the
+// weights staged as the projection stages them (binary: m > 0 counts as 1;
+// clip_negative: negative data under weight is treated as masked).
 hipError_t launch_frame_objective(const float* H, const float* C, const float* T,
-                                  const float* MT, int64_t f, int k, int64_t p, double* out,
-                                  hipStream_t s);
+                                  const float* MT, int64_t f, int k, int64_t p, int binary,
+                                  int clip_negative, double* out, hipStream_t s);
 
 // Masked-Gram projection: one persistent launch over all frames.
 struct GramArgs {
@@ -177,6 +195,7 @@ struct GramArgs {
   int iters;
   float eps;
   int clip_negative;
+  int binary;          // every positive weight counts as 1
   float* C_out;        // F x K
   int* queue;          // zeroed before the launch
   int* status;         // bits as staging, plus 16 = bad CSR entry

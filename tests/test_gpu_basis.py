@@ -111,15 +111,43 @@ def test_binary_weight_bitmask_bitwise(precision, n, ny, nx, k):
     lib = synth.make_cfg3(n=n, ny=ny, nx=nx, k0=min(k + 4, n), frames=1)
     V, M = lib.V, lib.M
     say("bitmask", precision, n, ny * nx, k)
-    W1, H1, J1, r1 = nmf.build_basis(dev(V), dev(M), k, 25, precision=precision, seed=4)
+    # a fresh handle and the bitmask build first, so that no captured graph of
+    # the float-weight build can stand in for the bitmask kernels
+    h = nmf.Handle(0)
     W2, H2, J2, r2 = nmf.build_basis(dev(V), dev(M), k, 25, precision=precision, seed=4,
-                                     flags=nmf.F_BINARY_WEIGHTS)
+                                     flags=nmf.F_BINARY_WEIGHTS, handle=h)
+    W1, H1, J1, r1 = nmf.build_basis(dev(V), dev(M), k, 25, precision=precision, seed=4, handle=h)
     assert np.array_equal(host(W1), host(W2)) and np.array_equal(host(H1), host(H2))
     assert np.array_equal(J1, J2)
     M3 = M * np.random.default_rng(1).uniform(0.5, 3.0, M.shape).astype(np.float32)
     W3, H3, J3, _ = nmf.build_basis(dev(V), dev(M3), k, 25, precision=precision, seed=4,
-                                    flags=nmf.F_BINARY_WEIGHTS)
+                                    flags=nmf.F_BINARY_WEIGHTS, handle=h)
     assert np.array_equal(host(W1), host(W3)) and np.array_equal(host(H1), host(H3))
+    h.close()
+
+
+def test_weight_storage_change_on_one_handle():
+    """Builds of one shape on one handle that switch between bitmask and float
+    weight storage each meet the oracle (the captured iteration graphs are
+    keyed by the weight storage)."""
+    lib = synth.make_cfg3(n=64, ny=30, nx=40, k0=12, frames=1)
+    n, p = lib.V.shape
+    g = np.random.default_rng(3)
+    Mf = (lib.M * g.uniform(0.5, 3.0, lib.M.shape)).astype(np.float32)
+    h = nmf.Handle(0)
+    say("storage switch: bitmask, then float weights, then bitmask")
+    runs = [(lib.M, nmf.F_BINARY_WEIGHTS), (Mf, 0), (lib.M, nmf.F_BINARY_WEIGHTS), (Mf, 0)]
+    W0 = prng.init_matrix(6, prng.MAT_W, n, 8)
+    H0 = prng.init_matrix(6, prng.MAT_H, 8, p)
+    for M, flags in runs:
+        W, H, J, _ = nmf.build_basis(dev(lib.V), dev(M), 8, 40, seed=6, flags=flags, handle=h)
+        Mo = (M > 0).astype(np.float64) if flags else M
+        Wo, Ho, Jo = nmf64.build_basis(lib.V, Mo, W0, H0, 40)
+        relJ = abs(objective64(lib.V, Mo, host(W), host(H)) - Jo[-1]) / Jo[-1]
+        print(f"  flags={flags} relJ={relJ:.2e}", flush=True)
+        assert relJ <= 1e-5
+        assert np.max(np.abs(J - Jo) / Jo) <= 1e-5
+    h.close()
 
 
 def test_binary_weight_bitmask_projection_bitwise():
@@ -196,16 +224,53 @@ def test_data_errors_and_guards():
     assert np.array_equal(host(W)[11], host(W0)[11])
 
 
-def test_tolerance_stop_and_normalisation():
+@pytest.mark.parametrize("c,tol", [(10, 1e-4), (7, 3e-4), (25, 1e-5)])
+def test_tolerance_stop_matches_oracle_rule(c, tol):
+    """The on-device stop rule (relative decrease of J over c iterations,
+    tested at multiples of c; the iteration at which it passes is the last)
+    stops at the iteration the oracle's rule picks from its own history, and
+    the histories agree."""
     lib = synth.make_cfg1(n=48, ny=40, nx=40, k0=6)
-    say("tol-stop")
-    W, H, J, rep = nmf.build_basis(dev(lib.V), dev(lib.M), 6, 2000, tol=1e-4, check_every=10)
-    assert rep["iters_run"] < 2000 and rep["iters_run"] % 10 == 0
-    assert len(J) == rep["iters_run"] + 1
+    n, p = lib.V.shape
+    T = 3000
+    say("tol-stop", c, tol)
+    W, H, J, rep = nmf.build_basis(dev(lib.V), dev(lib.M), 6, T, tol=tol, check_every=c, seed=3)
+    W0 = prng.init_matrix(3, prng.MAT_W, n, 6)
+    H0 = prng.init_matrix(3, prng.MAT_H, 6, p)
+    Wo, Ho, Jo, run = nmf64.build_basis_tol(lib.V, lib.M, W0, H0, T, c, tol)
+    print(f"  device stopped after {rep['iters_run']}, oracle after {run}", flush=True)
+    assert run < T
+    # the decisive relative decrease is not within rounding of tol, so both
+    # sides must take the same decision
+    t = run - 1
+    margin = abs((Jo[t - c] - Jo[t]) / Jo[t - c] - tol) / tol
+    assert margin > 1e-3
+    assert rep["iters_run"] == run
+    assert rep["status"] == 0
+    assert len(J) == run + 1
+    assert np.max(np.abs(J - Jo) / Jo) <= 1e-5
+    J64 = objective64(lib.V, lib.M, host(W), host(H))
+    assert abs(J64 - Jo[-1]) / Jo[-1] <= 1e-5
+
+
+def test_tolerance_not_met_warns_maxiter():
+    lib = synth.make_cfg1(n=48, ny=40, nx=40, k0=6)
+    say("tol-stop maxiter")
+    W, H, J, rep = nmf.build_basis(dev(lib.V), dev(lib.M), 6, 40, tol=1e-12, check_every=10)
+    assert rep["iters_run"] == 40 and rep["status"] == nmf.NMF_WARN_MAXITER
+
+
+def test_normalisation_matches_oracle():
+    """NMF_F_NORMALIZE_H equals the oracle's unit-L2 component normalisation
+    applied to the same build's unnormalised factors."""
+    lib = synth.make_cfg1(n=48, ny=40, nx=40, k0=6)
+    say("normalisation")
     Wn, Hn, Jn, _ = nmf.build_basis(dev(lib.V), dev(lib.M), 6, 50, flags=nmf.F_NORMALIZE_H)
     Wp, Hp, Jp, _ = nmf.build_basis(dev(lib.V), dev(lib.M), 6, 50)
-    assert np.allclose(np.linalg.norm(host(Hn), axis=1), 1.0, rtol=1e-6)
-    assert rel_model_err(np.ones_like(lib.V), host(Wn) @ host(Hn), host(Wp) @ host(Hp)) < 1e-6
+    Wo, Ho = nmf64.normalize_components(host(Wp), host(Hp))
+    assert np.max(np.abs(host(Hn) - Ho) / np.abs(Ho).max(axis=1, keepdims=True)) < 2e-7
+    assert np.max(np.abs(host(Wn) - Wo) / np.abs(Wo).max(axis=0, keepdims=True)) < 2e-7
+    assert np.array_equal(Jn, Jp)
 
 
 def test_cfg2_full_size_one_iteration():

@@ -154,3 +154,22 @@ def test_stis_timing_workload_meets_nnls_tolerance():
 # iterations at which every frame of the STIS-shaped timing workload meets the
 # 1e-4 model tolerance (the projection count the benchmark times)
 STIS_TOL_ITERS = 100000
+
+
+def test_frame_objective_follows_weight_flags():
+    """The per-frame objective of a projection uses the weights as the
+    projection staged them: with NMF_F_BINARY_WEIGHTS every positive weight
+    counts as 1, with NMF_F_CLIP_NEGATIVE negative data is masked."""
+    H = _basis(6, 900, seed=9)
+    T, MT = _frames(H, 5, seed=10, peak=1e4)
+    MT = MT * np.random.default_rng(11).uniform(0.5, 3.0, MT.shape).astype(np.float32)
+    T[0, :7] = -1.0
+    say("frame objective flags")
+    for flags in (nmf.F_BINARY_WEIGHTS | nmf.F_CLIP_NEGATIVE, nmf.F_CLIP_NEGATIVE):
+        for gram in (False, True):
+            C, obj, _ = nmf.project(dev(H), dev(T), dev(MT), 50, seed=1, flags=flags,
+                                    gram=gram, want_objective=True)
+            Mo = (MT > 0).astype(np.float64) if flags & nmf.F_BINARY_WEIGHTS else MT.astype(np.float64)
+            Mo = np.where(T < 0, 0.0, Mo)
+            Jo = nmf64.frame_objective(T, Mo, H, host(C))
+            assert np.max(np.abs(host(obj) - Jo) / Jo) < 1e-6

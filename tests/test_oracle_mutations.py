@@ -89,7 +89,65 @@ def project_num_unmasked(T, MT, H, C0, iters, eps=nmf64.EPS_FLOOR):
     return C
 
 
+def frame_objective_weight_squared(T, MT, H, C):
+    Th, MTw, _ = nmf64.prep(T, MT)
+    R = Th - np.asarray(C, float) @ np.asarray(H, float)
+    return np.sum(MTw * MTw * R * R, axis=1)
+
+
+def frame_objective_no_prep(T, MT, H, C):
+    R = np.asarray(T, float) - np.asarray(C, float) @ np.asarray(H, float)
+    return np.sum(np.asarray(MT, float) * R * R, axis=1)
+
+
+def frame_objective_transposed_sum(T, MT, H, C):
+    Th, MTw, _ = nmf64.prep(T, MT)
+    R = Th - np.asarray(C, float) @ np.asarray(H, float)
+    return np.sum(MTw * R * R, axis=0)[: Th.shape[0]]
+
+
+def subtract_ignores_scale(T, MT, H, C, scale=None):
+    return _orig_subtract(T, MT, H, C, None)
+
+
+def subtract_scales_data(T, MT, H, C, scale=None):
+    T, MT = np.asarray(T, float), np.asarray(MT, float)
+    model = np.asarray(C, float) @ np.asarray(H, float)
+    s = np.ones(T.shape[0]) if scale is None else np.asarray(scale, float)
+    resid = s[:, None] * T - model
+    resid[MT == 0] = np.nan
+    return model, resid
+
+
+def subtract_no_nan(T, MT, H, C, scale=None):
+    T = np.asarray(T, float)
+    model = np.asarray(C, float) @ np.asarray(H, float)
+    s = np.ones(T.shape[0]) if scale is None else np.asarray(scale, float)
+    return model, T - s[:, None] * model
+
+
+def stop_test_absolute(J, t, check_every, tol):
+    c = int(check_every)
+    return c > 0 and t >= c and t % c == 0 and (J[t - c] - J[t]) < tol
+
+
+def stop_test_off_by_one(J, t, check_every, tol):
+    c = int(check_every)
+    return c > 0 and t > c and (t - 1) % c == 0 and (J[t - 1 - c] - J[t - 1]) / J[t - 1 - c] < tol
+
+
+_orig_subtract = nmf64.subtract
+
 MUTANTS = {
+    "frame objective with squared weights": ("frame_objective", frame_objective_weight_squared),
+    "frame objective keeps masked data": ("frame_objective", frame_objective_no_prep),
+    "frame objective summed over the wrong axis": ("frame_objective",
+                                                   frame_objective_transposed_sum),
+    "subtraction ignores the scale": ("subtract", subtract_ignores_scale),
+    "subtraction scales the data instead of the model": ("subtract", subtract_scales_data),
+    "subtraction keeps masked residuals": ("subtract", subtract_no_nan),
+    "stop test on the absolute decrease": ("stop_test", stop_test_absolute),
+    "stop test one iteration late": ("stop_test", stop_test_off_by_one),
     "H-rule with squared weights": ("update_H", h_weight_squared),
     "H-rule denominator without weights": ("update_H", h_den_unweighted),
     "H-rule numerator/denominator swapped": ("update_H", h_swapped),
@@ -120,6 +178,11 @@ def _pin_suite():
     yield "masked garbage", pins.test_masked_garbage_is_ignored
     yield "fully masked", pins.test_fully_masked_row_and_column_keep_factors
     yield "prep flags", pins.test_prep_flags_bad_data_under_weight
+    yield "frame objective by hand", pins.test_frame_objective_hand_worked
+    yield "frame objective = NNLS cost", pins.test_frame_objective_equals_nnls_cost
+    yield "subtraction by hand", pins.test_subtract_hand_worked
+    yield "stop test by hand", pins.test_stop_test_hand_worked
+    yield "tolerant build", pins.test_build_basis_tol_stops_at_the_rule
 
 
 @contextlib.contextmanager

@@ -333,3 +333,100 @@ def test_normalisation_keeps_product():
     W2, H2 = nmf64.normalize_components(W, H)
     assert np.allclose(W2 @ H2, W @ H, rtol=1e-14)
     assert np.allclose(np.linalg.norm(H2, axis=1), 1.0, rtol=1e-14)
+
+
+# -------------------------------------------- per-frame objective (a8)
+
+def _golden_frames(name):
+    g = _golden(name)
+    arr = lambda x: np.array([[np.nan if v == "nan" else v for v in row] for row in x], float)
+    return g, arr
+
+
+def test_frame_objective_hand_worked():
+    """Per-frame Eq. 2 cost of a model c H (Sec. 4.1): worked by hand, with a
+    masked NaN pixel that must be ignored and a non-unit weight that must
+    enter linearly."""
+    g, arr = _golden_frames("frame_objective_2x3.json")
+    J = nmf64.frame_objective(arr(g["T"]), arr(g["MT"]), arr(g["H"]), arr(g["C"]))
+    assert np.array_equal(J, np.array(g["J"]))
+
+
+def test_frame_objective_equals_nnls_cost():
+    """The per-frame objective equals the quadratic form of the normal
+    equations, c G c^T - 2 b c^T + t^T diag(m) t (an independent route)."""
+    g = np.random.default_rng(91)
+    K, P, F = 4, 50, 3
+    H = g.uniform(0, 1, (K, P))
+    C = g.uniform(0, 2, (F, K))
+    T = g.uniform(0, 3, (F, P))
+    MT = g.uniform(0.1, 2, (F, P)) * (g.random((F, P)) > 0.2)
+    J = nmf64.frame_objective(T, MT, H, C)
+    for f in range(F):
+        G, b, c = nnls.normal_equations(H, T[f], MT[f])
+        assert abs(J[f] - nnls.cost(G, b, c, C[f])) <= 1e-12 * J[f]
+
+
+# ------------------------------------------------------ subtraction (a9)
+
+def test_subtract_hand_worked():
+    """Model and residual worked by hand, including the NaN pattern at the
+    zero-weight pixel and the per-frame scale."""
+    g, arr = _golden_frames("subtract_2x3.json")
+    model, resid = nmf64.subtract(arr(g["T"]), arr(g["MT"]), arr(g["H"]), arr(g["C"]),
+                                  scale=np.array(g["scale"]))
+    assert np.array_equal(model, arr(g["model"]))
+    want = arr(g["resid"])
+    assert np.array_equal(np.isnan(resid), np.isnan(want))
+    ok = ~np.isnan(want)
+    assert np.array_equal(resid[ok], want[ok])
+
+
+# ------------------------------------------------------ exact NNLS (a8)
+
+@pytest.mark.parametrize("seed", range(12))
+def test_bruteforce_nnls_matches_scipy(seed):
+    """The two exact NNLS routes (brute force over supports, scipy's
+    active-set solver) agree on random K <= 4 problems with and without
+    active constraints."""
+    g = np.random.default_rng(500 + seed)
+    K, P = 1 + seed % 4, 30
+    H = g.uniform(0, 1, (K, P)) ** 2
+    w_true = g.uniform(-0.5, 1.5, K)
+    t = np.maximum(w_true @ H + g.normal(0, 0.05, P), 0)
+    m = g.uniform(0.2, 2.0, P) * (g.random(P) > 0.1)
+    G, b, c = nnls.normal_equations(H, t, m)
+    wb, jb = nnls.nnls_bruteforce(G, b, c)
+    ws = nnls.nnls_scipy(H, t, m)
+    assert abs(nnls.cost(G, b, c, ws) - jb) <= 1e-10 * max(jb, 1e-12)
+    assert np.allclose(wb, ws, atol=1e-8 * max(1.0, np.abs(wb).max()))
+    assert nnls.kkt_residual(G, b, wb) < 1e-9
+
+
+# ------------------------------------------------- stopping rule (a6, f4)
+
+def test_stop_test_hand_worked():
+    """The relative-decrease rule on a hand-made history: with c = 2 and
+    tol = 0.1 the decreases over two iterations are 100->60 (0.4) at t = 2,
+    60->50 (0.167) at t = 4 and 50->47 (0.06) at t = 6, so it first passes
+    at t = 6; odd t are never tested."""
+    J = [100.0, 80.0, 60.0, 55.0, 50.0, 49.9, 47.0, 46.0]
+    passes = [t for t in range(len(J)) if nmf64.stop_test(J, t, 2, 0.1)]
+    assert passes == [6]
+    assert not nmf64.stop_test(J, 5, 2, 0.1)
+    assert not nmf64.stop_test(J, 6, 0, 0.1)
+
+
+def test_build_basis_tol_stops_at_the_rule():
+    """With the rule off the tolerant build equals the fixed-count build
+    bitwise; with it on it stops after the first iteration at which the rule
+    passes, and its history is the fixed-count history cut there."""
+    V, M, W, H = _tiny(92, n=8, p=12, k=2)
+    Wf, Hf, Jf = nmf64.build_basis(V, M, W, H, 200)
+    Wt, Ht, Jt, run = nmf64.build_basis_tol(V, M, W, H, 200, 0, 0.0)
+    assert run == 200 and np.array_equal(Wt, Wf) and np.array_equal(Jt, Jf)
+    Wt, Ht, Jt, run = nmf64.build_basis_tol(V, M, W, H, 200, 5, 1e-3)
+    first = next(t for t in range(5, 200, 5) if (Jf[t - 5] - Jf[t]) / Jf[t - 5] < 1e-3)
+    assert run == first + 1
+    Wr, Hr, Jr = nmf64.build_basis(V, M, W, H, run)
+    assert np.array_equal(Wt, Wr) and np.array_equal(Jt, Jr)
