@@ -1,24 +1,35 @@
 #!/usr/bin/env python3
 """Benchmark of the weighted multiplicative-update NMF hot path on one MI355X.
 
-Workload (STIS-shaped, synthetic): a reference library of N = 500 images of
-200 x 200 px (P = 40000) with a 12 px diagonal occulting wedge and weights
-1/(V + 0.01); a K = 30 basis is built with 1000 iterations of Eq. 3, then 50
-science frames (with injected ring disks at 1e-3) are projected onto it for
-1000 iterations (masked-Gram form, one persistent launch) and the model PSF
-is subtracted.  One step = all of that.
+Headline workload (MIRI-shaped precision study, synthetic): a reference
+library of N = 2000 images of 224 x 288 px (P = 64512) with a 4QPM-like cross
+mask and 2% bad pixels per image, binary weights stored as bitmasks; a
+K = 100 basis is built with 500 iterations of Eq. 3 in split-precision
+(bf16x3) products, then the library's science frames are projected onto it
+(masked-Gram form, one persistent launch, 500 iterations) and the model PSF
+is subtracted.  One step = all of that; ``value`` = basis iterations per
+second of the whole step (500 / step time), timed on the production path
+(iterations replayed from captured hipGraphs, no per-launch timing).
 
-Prints one JSON line.  ``value`` = basis iterations per second of the whole
-step (1000 / step time); the line also carries the GEMM TFLOP/s of the
-fused half-step kernels, projection frames/s, a ``roofline`` object for the
-dominant kernel (timed live with HIP events on the library's stream), the
-same figures for the other precision form under ``precision_forms`` (FP32
-and split-precision bf16x3), and a ``cpu_baseline`` object (the FP64 oracle
-on this host's cores).
+The same JSON line carries:
+  * ``precision_forms``: the step in both precision forms (FP32 and bf16x3),
+    each with its kernel times and a roofline for its dominant kernel;
+  * ``roofline``: the dominant kernel of the headline form; its duration is
+    the average over the launches of a separate instrumented step (HIP events
+    around every launch on the library's stream, which also turns graph
+    replay off), and ``traffic`` comes from stored hardware counters when
+    they were taken on the current kernel source;
+  * ``batched``: 4096 CSR frames with P_f ~ U{10000..64512} valid pixels
+    projected onto a K = 200 basis (built by the library from the same
+    library) for 300 iterations each in one persistent launch: frames/s and
+    per-frame p50/p99 latency from device timestamps;
+  * ``cpu_baseline``: the FP64 oracle, untuned, on this host's cores, on a
+    bounded sample of basis iterations of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -33,21 +44,43 @@ METRIC = "NMF iterations/s and GEMM TFLOP/s (% MFMA roofline); projected frames/
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
-# masked-Gram iterations after which every frame of this workload is within
-# 1e-4 of the exact weighted-NNLS model (checked by the GPU test suite)
-TOL_ITERS = 100000
+PEAKS = {"fp32": PEAK_FP32_TFLOPS, "bf16x3": PEAK_BF16_TFLOPS / 3.0}
 
 K_HRULE, K_WRULE, K_WFINISH, K_OBJ, K_PROJECT, K_SUBTRACT, K_OTHER = range(7)
 K_NAMES = ["hrule", "wrule", "wfinish", "objective", "project", "subtract", "other"]
+
+WORKLOADS = {
+    "miri": dict(make="make_cfg3", k=100, iters=500, frames=8, proj_iters=500, binary=True,
+                 shape=[224, 288],
+                 name="MIRI-shaped basis build (2000 images of 224x288 px, K=100, 500 iterations, "
+                      "binary weights as bitmasks) + projection and subtraction of 8 frames"),
+    "stis": dict(make="make_cfg2", k=30, iters=1000, frames=50, proj_iters=1000, binary=False,
+                 shape=[200, 200],
+                 name="STIS-shaped basis build (500 images of 200x200 px, K=30, 1000 iterations, "
+                      "weights mask/(V+0.01)) + projection and subtraction of 50 frames"),
+}
+# hardware counters stored for the dominant kernel (see profiles/)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_wide_miri_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2309_04623_amd", "csrc", "k_wide.hip")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(lib, k, seconds):
     """The FP64 oracle, untuned, on this host's cores: basis iterations of the
-    same workload until ``seconds`` have elapsed."""
+    same workload until ``seconds`` have elapsed (at least one)."""
     from oracle import nmf64, prng
     try:
         from threadpoolctl import threadpool_info
@@ -68,8 +101,22 @@ def cpu_baseline(lib, k, seconds):
         if el >= seconds:
             break
     return {"value": it / el, "unit": "iterations/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{it} FP64 basis iterations of the same N={n} P={p} K={k} workload "
-                      f"({el:.1f} s)"}
+            "cpu": cpu_model(),
+            "sample": f"{it} FP64 basis iterations (Eq. 3, H then W) of the same N={n} P={p} "
+                      f"K={k} library from the seeded start ({el:.1f} s)"}
+
+
+def stored_traffic():
+    """HBM bytes per launch from stored counters, if they were taken on the
+    current source of the dominant kernel."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return rec
 
 
 def main():
@@ -77,23 +124,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
-    ap.add_argument("--iters", type=int, default=1000)
-    ap.add_argument("--proj-iters", type=int, default=1000)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="miri", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3"])
+    ap.add_argument("--iters", type=int, default=None, help="basis iterations per step")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--skip-tolerance", action="store_true",
-                    help="do not time the projections to the 1e-4 tolerance")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 4096-frame batched leg")
+    ap.add_argument("--batched-frames", type=int, default=4096)
     ap.add_argument("--single-precision", action="store_true",
-                    help="time only --precision (by default the other precision form is "
-                         "timed too and reported under precision_forms)")
+                    help="time only --precision (by default both precision forms are timed)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain elementwise copy of MIB MiB (reads and writes "
                          "MIB MiB), the reference dispatch for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(frames and pixels would shard across GPUs; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU only: this build has no multi-GPU path (pixels of "
+              "the basis build and frames of the projection would shard across GPUs)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -104,9 +151,12 @@ def main():
         sys.exit(1)
     nmf.lib()  # fails loudly if the HIP library was not built
 
-    K = 30
-    log("generating the STIS-shaped workload ...")
-    lib = synth.make_cfg2()
+    W_ = WORKLOADS[args.workload]
+    K = W_["k"]
+    iters = args.iters or W_["iters"]
+    flags = nmf.F_BINARY_WEIGHTS if W_["binary"] else 0
+    log(f"generating the {args.workload} workload ...")
+    lib = getattr(synth, W_["make"])(frames=W_["frames"])
     n, p = lib.V.shape
     f = lib.T.shape[0]
     dev = torch.device("cuda:0")
@@ -126,113 +176,89 @@ def main():
         log(f"calibration copy of {args.copy_calibration} MiB done")
 
     def step(prec):
-        W, H, J, rep = nmf.build_basis(V, M, K, args.iters, precision=prec, seed=1, handle=h)
-        C, _ = nmf.project(H, T, MT, args.proj_iters, precision=prec, seed=2, gram=True,
-                           handle=h)
+        W, H, J, rep = nmf.build_basis(V, M, K, iters, precision=prec, seed=1, flags=flags,
+                                       handle=h)
+        C, _ = nmf.project(H, T, MT, W_["proj_iters"], seed=2, gram=True, flags=flags, handle=h)
         model, resid = nmf.subtract(H, C, T, MT, handle=h)
         return J, rep
 
     def measure(prec):
         """Warm-up, then exactly ``steps`` timed steps bracketed by device
-        synchronisation; kernel time per launch class from the library's
-        own HIP events on its stream."""
+        synchronisation (graph replay, no per-launch timing); then one
+        instrumented step for per-kernel device times."""
         for i in range(args.warmup):
             log(f"[{prec}] warmup step {i + 1}/{args.warmup}")
             step(prec)
-        torch.cuda.synchronize()
-        nmf.profile_enable(h, True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.steps):
             J, rep = step(prec)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        prof = {K_NAMES[c]: nmf.profile_get(h, c) for c in range(7)}
-        nmf.profile_enable(h, False)
         log(f"[{prec}] timed {args.steps} steps: {el:.3f} s; final J {J[-1]:.6e} "
             f"rel {rep['objective_rel']:.3e}")
-        return el, prof
+        nmf.profile_enable(h, True)
+        step(prec)
+        torch.cuda.synchronize()
+        prof = {K_NAMES[c]: nmf.profile_get(h, c) for c in range(7)}
+        nmf.profile_enable(h, False)
+        return el, prof, J
 
-    def summarize(prec, el, prof):
-        # algorithmic work of one basis iteration: six N x K x P contractions
-        flops_iter = 12.0 * n * K * p
-        gemm_ms = prof["hrule"][1] + prof["wrule"][1]
-        basis_ms = sum(prof[c][1] for c in ("hrule", "wrule", "wfinish", "objective"))
-        proj_ms = prof["project"][1] + prof["subtract"][1]
-        # Dominant kernel: the fused half-step with the larger summed time.
+    def summarize(prec, el, prof, J):
+        flops = 6.0 * n * K * p  # per half-step launch: Y, num, den (N x K x P each)
+        # algorithmic HBM bytes per launch: the data once (4 B/px) and the
+        # weights (1/8 B/px as bitmask, 4 B/px as FP32), plus the factors
+        wbytes = 0.125 if W_["binary"] else 4.0
+        bytes_ = (4.0 + wbytes) * n * p + 4.0 * 3 * K * (n + p)
         dom = max(("hrule", "wrule"), key=lambda c: prof[c][1])
         cnt, tot = prof[dom]
         avg_s = tot * 1e-3 / cnt
-        # per launch: 3 N K P multiply-adds (Y, num, den), and the data stream
-        # (value + weight, 8 B per element) plus the factors read and written
-        flops = 6.0 * n * K * p
-        bytes_ = 8.0 * n * p + 4.0 * (n * K + 2 * K * p) if dom == "hrule" else \
-            8.0 * n * p + 4.0 * (2 * n * K + K * p)
-        peak_fl = PEAK_FP32_TFLOPS if prec == "fp32" else PEAK_BF16_TFLOPS / 3
-        t_mfma = flops / (peak_fl * 1e12)
+        peak = PEAKS[prec]
+        t_mfma = flops / (peak * 1e12)
         t_hbm = bytes_ / (PEAK_HBM_GBS * 1e9)
         if t_mfma >= t_hbm:
-            roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": peak_fl,
+            roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": peak,
                     "unit": "TFLOP/s"}
         else:
             roof = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": PEAK_HBM_GBS,
                     "unit": "GB/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
         roof["traffic"] = None
-        roof["kernel"] = f"k_dual ({dom} half-step), avg {avg_s * 1e6:.2f} us over {cnt} launches"
+        roof["kernel"] = (f"k_wide ({dom} half-step, {prec}), avg {avg_s * 1e6:.2f} us over "
+                          f"{cnt} launches of the instrumented step")
+        roof["algorithmic_flops_per_launch"] = flops
+        roof["algorithmic_bytes_per_launch"] = bytes_
         roof["hbm_GBs_algorithmic"] = bytes_ / avg_s / 1e9
         roof["mfma_TFLOPs_algorithmic"] = flops / avg_s / 1e12
+        if prec == "bf16x3":
+            roof["peak_note"] = "dense bf16 2500 TFLOP/s / 3 products per split-precision product"
+        gemm_ms = prof["hrule"][1] + prof["wrule"][1]
+        basis_ms = sum(prof[c][1] for c in ("hrule", "wrule", "wfinish", "objective"))
         return {
-            "iterations_per_s": args.iters * args.steps / el,
+            "iterations_per_s": iters * args.steps / el,
             "ms_per_step": el * 1e3 / args.steps,
-            "gemm_tflops": flops_iter * args.iters * args.steps / (gemm_ms * 1e-3) / 1e12,
-            "basis_iters_per_s_device": args.iters * args.steps / (basis_ms * 1e-3),
-            "frames_per_s": f * args.steps / (proj_ms * 1e-3) if proj_ms > 0 else None,
-            "kernel_ms_per_step": {c: prof[c][1] / args.steps for c in K_NAMES},
-            "kernel_launches_per_step": {c: prof[c][0] // args.steps for c in K_NAMES},
+            "gemm_tflops": 12.0 * n * K * p * iters / (gemm_ms * 1e-3) / 1e12,
+            "basis_iters_per_s_device": iters / (basis_ms * 1e-3),
+            "final_objective": float(J[-1]),
+            "kernel_ms_per_step": {c: prof[c][1] for c in K_NAMES},
+            "kernel_launches_per_step": {c: prof[c][0] for c in K_NAMES},
             "roofline": roof,
         }
 
-    def to_tolerance():
-        """Frames/s of projections that reach the 1e-4 model tolerance: the
-        50 frames run TOL_ITERS masked-Gram iterations (the count at which a
-        GPU test finds every frame within 1e-4 of the exact weighted-NNLS
-        model), against the plain method (direct form, FP32), timed over
-        1000 iterations and scaled to TOL_ITERS (its time is linear in the
-        count)."""
-        _, Hb, _, _ = nmf.build_basis(V, M, K, args.iters, seed=1, handle=h)
-        nmf.project(Hb, T, MT, TOL_ITERS, seed=2, gram=True, handle=h)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            nmf.project(Hb, T, MT, TOL_ITERS, seed=2, gram=True, handle=h)
-        torch.cuda.synchronize()
-        el = (time.perf_counter() - t0) / args.steps
-        nmf.project(Hb, T, MT, 1000, seed=2, handle=h)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            nmf.project(Hb, T, MT, 1000, seed=2, handle=h)
-        torch.cuda.synchronize()
-        el_plain = (time.perf_counter() - t0) / args.steps * (TOL_ITERS / 1000)
-        log(f"to tolerance: {el * 1e3:.2f} ms per batch; plain direct form "
-            f"{el_plain * 1e3:.1f} ms (scaled)")
-        return {"tolerance": 1e-4, "iterations": TOL_ITERS, "frames": f,
-                "form": "masked-Gram, one persistent launch, FP32",
-                "ms_per_batch": el * 1e3, "frames_per_s": f / el,
-                "plain_fp32_direct_frames_per_s": f / el_plain,
-                "plain_note": "direct form timed over 1000 iterations, scaled linearly",
-                "speedup_vs_plain": el_plain / el}
+    forms = {}
+    order = [args.precision] + ([] if args.single_precision else
+                                [q for q in ("fp32", "bf16x3") if q != args.precision])
+    for prec in order:
+        forms[prec] = summarize(prec, *measure(prec))
+    main_sum = forms[args.precision]
+    traffic = stored_traffic()
+    if traffic and traffic.get("precision") == args.precision:
+        main_sum["roofline"]["traffic"] = traffic["hbm_bytes_per_launch"]
+        main_sum["roofline"]["traffic_source"] = traffic.get("source")
 
-    main_sum = summarize(args.precision, *measure(args.precision))
-    tol = None if args.skip_tolerance else to_tolerance()
-    others = {}
-    if not args.single_precision:
-        for prec in ("fp32", "bf16x3"):
-            if prec != args.precision:
-                others[prec] = summarize(prec, *measure(prec))
-        for o in others.values():
-            o["roofline"].pop("traffic", None)
+    batched = None
+    if not args.no_batched and args.workload == "miri":
+        batched = batched_leg(args, nmf, synth, lib, V, M, h, torch)
 
     out = {
         "metric": METRIC,
@@ -245,25 +271,64 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "bf16x3",
+        "dtype": "bf16x3" if args.precision == "bf16x3" else "f32",
         "data": "synthetic",
-        "config": {"workload": "STIS-shaped basis build + projection + subtraction",
-                   "images": n, "pixels": p, "image_shape": [200, 200], "k": K,
-                   "basis_iters": args.iters, "frames": f, "proj_iters": args.proj_iters,
-                   "projection": "masked-Gram", "precision": args.precision},
+        "config": {"workload": W_["name"], "images": n, "pixels": p,
+                   "image_shape": W_["shape"], "k": K, "basis_iters": iters, "frames": f,
+                   "proj_iters": W_["proj_iters"], "weights": "binary bitmask" if W_["binary"]
+                   else "FP32", "projection": "masked-Gram", "precision": args.precision},
     }
-    for key in ("gemm_tflops", "basis_iters_per_s_device", "frames_per_s", "kernel_ms_per_step",
+    for key in ("gemm_tflops", "basis_iters_per_s_device", "kernel_ms_per_step",
                 "kernel_launches_per_step", "roofline"):
         out[key] = main_sum[key]
-    if tol:
-        out["projection_to_tolerance"] = tol
-    if others:
-        out["precision_forms"] = others
+    out["precision_forms"] = {q: {k: v for k, v in s.items() if k != "kernel_launches_per_step"}
+                              for q, s in forms.items()}
+    if batched:
+        out["batched"] = batched
     if not args.no_cpu_baseline:
         log(f"timing the FP64 oracle on host cores for ~{args.cpu_seconds:.0f} s ...")
         out["cpu_baseline"] = cpu_baseline(lib, K, args.cpu_seconds)
     h.close()
     print(json.dumps(out), flush=True)
+
+
+def batched_leg(args, nmf, synth, lib, V, M, h, torch):
+    """4096 ragged frames (P_f ~ U{10000..64512} valid pixels near the star,
+    outside the cross) projected onto a K = 200 basis, 300 iterations each,
+    in one persistent launch."""
+    K2, ITERS = 200, 300
+    log("building the K = 200 basis for the batched leg ...")
+    _, Hb, _, _ = nmf.build_basis(V, M, K2, 30, precision="bf16x3", seed=3,
+                                  flags=nmf.F_BINARY_WEIGHTS, handle=h)
+    log(f"generating {args.batched_frames} ragged frames ...")
+    rag = synth.make_ragged(lib.H0, 224, 288, args.batched_frames, 10000, 64512)
+    dev = V.device
+    off = torch.from_numpy(rag.offsets).to(dev)
+    pix = torch.from_numpy(rag.pix).to(dev)
+    val = torch.from_numpy(rag.val).to(dev)
+    kw = dict(seed=4, flags=nmf.F_BINARY_WEIGHTS, want_ticks=True, handle=h)
+    nmf.project_ragged(Hb, off, pix, val, None, ITERS, **kw)  # warm-up (captures the graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        C, ticks, _ = nmf.project_ragged(Hb, off, pix, val, None, ITERS, **kw)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    tk = ticks.cpu().numpy().reshape(-1, 2)
+    khz = nmf.device_clock_khz(h)
+    lat_us = (tk[:, 1] - tk[:, 0]) / khz * 1e3
+    F = rag.f
+    nnz = int(rag.offsets[-1])
+    sizes = np.diff(rag.offsets)
+    flops = float(np.sum(2.0 * K2 * K2 * sizes + 2.0 * K2 * sizes) + F * ITERS * 2.0 * K2 * K2)
+    log(f"batched: {F} frames in {el * 1e3:.2f} ms")
+    return {"frames": F, "k": K2, "iters": ITERS, "nnz": nnz,
+            "pixels_per_frame": [int(sizes.min()), int(sizes.max())],
+            "form": "masked-Gram, CSR frames, one persistent launch (hipGraph), FP32 products",
+            "ms_per_batch": el * 1e3, "frames_per_s": F / el,
+            "latency_us_p50": float(np.percentile(lat_us, 50)),
+            "latency_us_p99": float(np.percentile(lat_us, 99)),
+            "algorithmic_tflops": flops / el / 1e12}
 
 
 if __name__ == "__main__":

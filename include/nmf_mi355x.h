@@ -93,7 +93,9 @@ enum nmf_flags {
 /* Iteration parameters.  Fill with nmf_params_default() first. */
 typedef struct {
   uint32_t struct_size;  /* = sizeof(nmf_params)                              */
-  int32_t k;             /* number of components, 1 <= k <= min(n, p)        */
+  int32_t k;             /* number of components, 1 <= k <= min(n, p); the
+                            fused passes take k <= 224, the masked-Gram
+                            projection k <= 200 (else NMF_ERR_UNSUPPORTED) */
   int32_t max_iter;      /* iterations of Eq. 3 (fixed count when tol == 0)   */
   int32_t check_every;   /* objective test cadence for tol (0 = never)        */
   double tol;            /* stop when (J[t-c] - J[t]) / J[t-c] < tol          */
@@ -102,8 +104,9 @@ typedef struct {
   int32_t flags;         /* OR of enum nmf_flags                              */
   float floor_eps;       /* non-negativity floor applied after each update    */
   int32_t split;         /* row chunks of the split half-step; 0 = auto      */
-  int32_t waves;         /* waves per workgroup of the fused passes (1, 2, 4);
-                            0 = auto                                          */
+  int32_t waves;         /* waves per workgroup of the fused passes (1, 2, 4;
+                            k <= 64 only: from k = 65 on a workgroup of four
+                            waves owns four column tiles); 0 = auto          */
   int32_t pipeline;      /* load pipelining of the fused passes: 1 = operands
                             per tile, 2 = operands and data one tile ahead,
                             3 = operands one and data two tiles ahead
@@ -241,6 +244,54 @@ double nmf_device_clock_khz(nmf_handle h);
 int nmf_subtract(nmf_handle h, const float* H, const float* C, const float* T,
                  const float* M_T, int64_t f, int64_t k, int64_t p, const float* scale,
                  float* model_out, float* resid_out, void* stream);
+
+/* ---- reference selection ---------------------------------------------------
+ * Sec. 4.1: the target frames are compared with the reference library and
+ * the closest frames, by the Euclidean norm (the cost the factorisation
+ * minimises), build the basis; Sec. 5.3 finds this the largest SNR gain.
+ *   dist[f, n] = sum over pixels j with M_T[f, j] > 0 and M[n, j] > 0 of
+ *                (T[f, j] - V[n, j])^2     (data under zero weight ignored)
+ * summed in FP32 over 64-pixel chunks and in FP64 across chunks.
+ *   idx_out[f, r] (r < n_sel) = the reference of rank r for target f, by
+ *   increasing distance, equal distances by increasing reference index.
+ *   V, M: n x p library and weights; T, M_T: f x p targets and weights
+ *   dist_out: nullable f x n doubles (device); idx_out: f x n_sel int32
+ *   (device).  n < 2^31, f <= 65535, 1 <= n_sel <= n.
+ * Synchronous.  Errors: NMF_ERR_ARG / NMF_ERR_SHAPE before any work;
+ * NMF_ERR_NONFINITE when data under positive weight are not finite.      */
+int nmf_closest_frames(nmf_handle h, const float* V, const float* M, int64_t n, int64_t p,
+                       const float* T, const float* M_T, int64_t f, int64_t n_sel,
+                       double* dist_out, int32_t* idx_out, void* stream);
+
+/* ---- best factor -------------------------------------------------------------
+ * Sec. 2 and Sec. 4.1 (best factor finding, after Ren et al. 2018, which
+ * the paper cites without restating): the per-frame scale s_f of the model
+ * PSF m = c_f H applied before subtraction.  Read here as the s minimising
+ * the variance of t - s m over the pixels with M_T > 0 (and region > 0 when
+ * a region is given, to keep the circumstellar signal out of the fit):
+ *   s_f = cov(t, m) / var(m), clamped to [s_lo, s_hi];
+ *   s_f = 1 with fewer than two such pixels or var(m) <= 1e-12 mean(m^2).
+ * Moments accumulated in FP64.  Feed scale_out to nmf_subtract.
+ *   H: k x p; C: f x k; T, M_T: f x p; region: nullable p; scale_out: f
+ *   floats (device).  Synchronous.  Errors: NMF_ERR_ARG (null, s_lo > s_hi). */
+int nmf_best_factor(nmf_handle h, const float* H, const float* C, const float* T,
+                    const float* M_T, const float* region, int64_t f, int64_t k, int64_t p,
+                    float s_lo, float s_hi, float* scale_out, void* stream);
+
+/* ---- component-by-component basis construction ------------------------------
+ * The basis-build variant of the package the paper modifies (Sec. 2): stage
+ * j = 1..k runs nmf_build_basis with j components from the j - 1 components
+ * of stage j - 1 plus one new component, W column j - 1 = U(0,1) of matrix 3
+ * at index r * k + j - 1 and H row j - 1 = U(0,1) of matrix 4 at index
+ * (j - 1) * p + c (their places in n x k and k x p matrices; the stream of
+ * nmf_init_uniform).  prm->max_iter (and the stop rule) apply per stage.
+ *   W_out, H_out: n x k and k x p results of the last stage
+ *   obj_stages: [host] nullable, k doubles: the Eq. 2 cost after each stage
+ *   rep: iters_run = iterations over all stages, objective of the last one
+ * Errors and warnings as nmf_build_basis (the first failing stage's).     */
+int nmf_build_basis_sequential(nmf_handle h, const float* V, const float* M, int64_t n, int64_t p,
+                               const nmf_params* prm, float* W_out, float* H_out,
+                               double* obj_stages, nmf_report* rep, void* stream);
 
 /* ---- learned warm start of the projection ---------------------------------
  * Not part of the paper's method: a small network predicts each frame's

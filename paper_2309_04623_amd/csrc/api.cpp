@@ -292,7 +292,8 @@ int check_params(const nmf_params* prm, int64_t rows, int64_t cols, bool need_k_
 }
 
 int kp_for(int k) { return round_up(k, 32); }
-constexpr int KP_MAX = 128;
+constexpr int KP_MAX = 224;  // K <= 224
+constexpr int KP_WIDE = 96;   // from here on the wide-basis half-step runs
 constexpr int64_t DIM_MAX = (int64_t)1 << 30;
 
 int check_dims(int64_t a, int64_t b, const char* what) {
@@ -446,6 +447,13 @@ constexpr int SIMDS = 1024;  // 256 compute units x 4
 // (bf16x3).  The autotuner replaces these per shape on request.
 PassCfg cfg_whole(int col_tiles, int RT, int KP, int prec, int req_nw) {
   PassCfg c;
+  if (KP >= KP_WIDE) {  // one workgroup per four column tiles, all rows
+    c.nw = 4;
+    c.splits = 1;
+    c.tiles_per_split = RT;
+    c.pipe = 0;
+    return c;
+  }
   const int cap = SIMDS * occupancy_for(KP);
   c.nw = KP >= 128 ? 2 : 1;  // one wave per workgroup spills at KP = 128
   if (req_nw > 0) {
@@ -468,6 +476,17 @@ PassCfg cfg_whole(int col_tiles, int RT, int KP, int prec, int req_nw) {
 
 PassCfg cfg_split(int col_tiles, int RT, int KP, int prec, int req_split, int req_nw) {
   PassCfg c;
+  if (KP >= KP_WIDE) {
+    // about one workgroup (four waves, one per SIMD) per compute unit
+    const int groups = wide_groups(col_tiles);
+    int S = req_split > 0 ? req_split : std::max(1, (256 + groups - 1) / groups);
+    S = std::min(S, std::max(1, RT / 2));
+    c.nw = 4;
+    c.tiles_per_split = (RT + S - 1) / S;
+    c.splits = (RT + c.tiles_per_split - 1) / c.tiles_per_split;
+    c.pipe = 0;
+    return c;
+  }
   c.nw = req_nw > 0 ? req_nw : (prec == NMF_PREC_FP32 || KP > 64 ? 4 : 2);
   int S = req_split > 0 ? req_split : std::max(1, 256 / std::max(1, col_tiles));
   S = std::min(S, std::max(1, RT / c.nw));
@@ -475,6 +494,20 @@ PassCfg cfg_split(int col_tiles, int RT, int KP, int prec, int req_split, int re
   c.splits = (RT + c.tiles_per_split - 1) / c.tiles_per_split;
   c.pipe = pipe_for(KP, 0);
   return c;
+}
+
+// Launches one fused half-step over ``col_tiles`` column tiles with the
+// shape ``c``: the wide-basis kernel from KP_WIDE components on, else the
+// single-column-tile kernel.
+hipError_t launch_pass(int prec, int KP, int mode, const PassCfg& c, const DualArgs& a,
+                       int col_tiles, hipStream_t s) {
+  if (KP >= KP_WIDE) return launch_wide(prec, KP, mode, a, c.splits, s);
+  return launch_dual(prec, KP, mode, c.nw, c.pipe, a, col_tiles, c.splits, s);
+}
+
+// Number of objective partials (one per workgroup) of a launch_pass.
+int pass_blocks(int KP, const PassCfg& c, int col_tiles) {
+  return (KP >= KP_WIDE ? wide_groups(col_tiles) : col_tiles) * c.splits;
 }
 
 // Times candidate launch shapes of one fused half-step on the staged data
@@ -637,8 +670,11 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   if ((rc = factor_alloc(h, "GH", (int)c.p, p_pad, KP, &Hf)) || (rc = ws(h, "gqueue", 1, &queue)) ||
       (rc = ws(h, "gstat", 1, &stat)))
     return rc;
-  const bool sorted = ragged && c.f <= MAX_SORT_FRAMES && c.f > 1;
+  const bool sorted = ragged && c.f > 1;
+  int* sort_tmp = nullptr;
   if (sorted && (rc = ws(h, "gorder", (size_t)c.f, &order))) return rc;
+  if (sorted && c.f > MAX_SORT_FRAMES && (rc = ws(h, "gsorttmp", 4 * (size_t)c.f, &sort_tmp)))
+    return rc;
   const bool warm = (c.prm->flags & NMF_F_WARM_START) != 0;
   if (warm && !c.C_init) return fail(NMF_ERR_ARG, "NMF_F_WARM_START needs C_init");
   int* fb = nullptr;
@@ -675,7 +711,8 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
     if ((e = timed(h, NMF_K_OTHER, s, [&]() { return launch_set_int(stat, 0, s); }))) return e;
     if ((e = timed(h, NMF_K_OTHER, s, [&]() { return launch_factor_fill(fa, s); }))) return e;
     if (sorted &&
-        (e = timed(h, NMF_K_OTHER, s, [&]() { return launch_frame_order(c.offsets, a.F, order, s); })))
+        (e = timed(h, NMF_K_OTHER, s,
+                   [&]() { return launch_frame_order(c.offsets, a.F, order, sort_tmp, s); })))
       return e;
     return timed(h, NMF_K_PROJECT, s, [&]() { return launch_gram(KP, ragged, a, 0, s, nullptr); });
   };
@@ -686,7 +723,7 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
               (uint64_t)c.val, (uint64_t)c.wt, (uint64_t)c.C_init, (uint64_t)c.C_out,
               (uint64_t)c.ticks, (uint64_t)c.prm->seed, (uint64_t)c.prm->max_iter,
               (uint64_t)c.prm->flags, (uint64_t)__builtin_bit_cast(uint32_t, c.prm->floor_eps),
-              (uint64_t)Hf.m, (uint64_t)queue, (uint64_t)stat, (uint64_t)order, (uint64_t)fb});
+              (uint64_t)Hf.m, (uint64_t)queue, (uint64_t)stat, (uint64_t)order, (uint64_t)sort_tmp, (uint64_t)fb});
   HIP_TRY(hipEventRecord(h->ev0, s));
   HIP_TRY(run_graph(h, key, s, enqueue));
   HIP_TRY(hipEventRecord(h->ev1, s));
@@ -734,7 +771,7 @@ int nmf_objective(nmf_handle h, const float* V, const float* M, const float* W, 
   if (precision != NMF_PREC_FP32 && precision != NMF_PREC_BF16X3)
     return fail(NMF_ERR_ARG, "unknown precision");
   const int KP = kp_for(k);
-  if (KP > KP_MAX) return fail(NMF_ERR_UNSUPPORTED, "k > 128 is not supported by this build");
+  if (KP > KP_MAX) return fail(NMF_ERR_UNSUPPORTED, "k > 224 is not supported by this build");
   if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
   DeviceGuard g(h->device);
   hipStream_t s = (hipStream_t)stream;
@@ -759,8 +796,8 @@ int nmf_objective(nmf_handle h, const float* V, const float* M, const float* W, 
   DualArgs a = pass_args(D, Mw, n_pad / 32, p_pad, (int)p, Wf, Hf.t, k, 0.f);
   a.Jpart = part;
   const PassCfg pc = cfg_whole(p_pad / 32, n_pad / 32, KP, precision, 0);
-  LAUNCH(NMF_K_OBJECTIVE, launch_dual(precision, KP, MODE_OBJ, pc.nw, pc.pipe, a, p_pad / 32, 1, s));
-  LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, p_pad / 32, Jdev, nullptr, s));
+  LAUNCH(NMF_K_OBJECTIVE, launch_pass(precision, KP, MODE_OBJ, pc, a, p_pad / 32, s));
+  LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, pass_blocks(KP, pc, p_pad / 32), Jdev, nullptr, s));
   int st = 0;
   HIP_TRY(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(J_out, Jdev, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -786,7 +823,7 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
     return fail(NMF_ERR_ARG, "forbidden aliasing between arguments");
   const int K = prm->k;
   const int KP = kp_for(K);
-  if (KP > KP_MAX) return fail(NMF_ERR_UNSUPPORTED, "k > 128 is not supported by this build");
+  if (KP > KP_MAX) return fail(NMF_ERR_UNSUPPORTED, "k > 224 is not supported by this build");
   if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
   const int T = prm->max_iter;
   const int prec = prm->precision;
@@ -864,7 +901,7 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   B.Mb = BbT;
   B.tiles_per_split = cb.tiles_per_split;
   B.partial = partial;
-  if (prm->flags & NMF_F_AUTOTUNE) {
+  if ((prm->flags & NMF_F_AUTOTUNE) && KP < KP_WIDE) {
     const std::string ka = key_of("tuneA", {(uint64_t)n, (uint64_t)p, (uint64_t)KP, (uint64_t)prec});
     const std::string kb = key_of("tuneB", {(uint64_t)n, (uint64_t)p, (uint64_t)KP, (uint64_t)prec});
     if ((rc = autotune_pass(h, ka, prec, KP, A, ptile, ntile, false, s, &ca))) return rc;
@@ -875,7 +912,7 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   }
   FinishArgs F = finish_args(partial, cb.splits, Wf, (int)n, K, eps, prec);
   F.Jpart = part;
-  F.nJ = ptile;
+  F.nJ = pass_blocks(KP, ca, ptile);
   F.Jhist = Jhist;
   F.iter = iter;
   F.status = stat;
@@ -902,10 +939,10 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
     hipError_t e;
     for (int i = 0; i < count; ++i) {
       if ((e = timed(h, NMF_K_HRULE, s,
-                     [&]() { return launch_dual(prec, KP, MODE_UPDATE, ca.nw, ca.pipe, A, ptile, 1, s); })))
+                     [&]() { return launch_pass(prec, KP, MODE_UPDATE, ca, A, ptile, s); })))
         return e;
       if ((e = timed(h, NMF_K_WRULE, s, [&]() {
-             return launch_dual(prec, KP, MODE_SPLIT, cb.nw, cb.pipe, B, ntile, cb.splits, s);
+             return launch_pass(prec, KP, MODE_SPLIT, cb, B, ntile, s);
            })))
         return e;
       if ((e = timed(h, NMF_K_WFINISH, s, [&]() { return launch_finish(F, s); }))) return e;
@@ -967,8 +1004,8 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   }
   HIP_TRY(loop_err);
   // Objective after the last iteration, stored at Jhist[iterations done].
-  LAUNCH(NMF_K_OBJECTIVE, launch_dual(prec, KP, MODE_OBJ, ca.nw, ca.pipe, A, ptile, 1, s));
-  LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, ptile, Jhist, stat, s, iter));
+  LAUNCH(NMF_K_OBJECTIVE, launch_pass(prec, KP, MODE_OBJ, ca, A, ptile, s));
+  LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, pass_blocks(KP, ca, ptile), Jhist, stat, s, iter));
   if (prm->flags & NMF_F_NORMALIZE_H) LAUNCH(NMF_K_OTHER, launch_normalize(Hf.t, KP, p_pad, K, Wf.t, n_pad, s));
   LAUNCH(NMF_K_OTHER, launch_factor_out(Wf.t, (int)n, n_pad, K, KP, 0, W_out, s));
   LAUNCH(NMF_K_OTHER, launch_factor_out(Hf.t, (int)p, p_pad, K, KP, 1, H_out, s));
@@ -1062,7 +1099,7 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
   }
   if (prm->flags & NMF_F_WARM_START)
     return fail(NMF_ERR_UNSUPPORTED, "NMF_F_WARM_START needs the masked-Gram form");
-  if (KP > KP_MAX) return fail(NMF_ERR_UNSUPPORTED, "k > 128 is not supported by this build");
+  if (KP > KP_MAX) return fail(NMF_ERR_UNSUPPORTED, "k > 224 is not supported by this build");
   if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
   const int prec = prm->precision;
   DeviceGuard g(h->device);
@@ -1106,7 +1143,7 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
   B.partial = partial;
   FinishArgs F = finish_args(partial, cb.splits, Cf, (int)f, K, prm->floor_eps, prec);
   for (int it = 0; it < prm->max_iter; ++it) {
-    LAUNCH(NMF_K_PROJECT, launch_dual(prec, KP, MODE_SPLIT, cb.nw, cb.pipe, B, ftile, cb.splits, s));
+    LAUNCH(NMF_K_PROJECT, launch_pass(prec, KP, MODE_SPLIT, cb, B, ftile, s));
     LAUNCH(NMF_K_PROJECT, launch_finish(F, s));
   }
   LAUNCH(NMF_K_OTHER, launch_factor_out(Cf.t, (int)f, f_pad, K, KP, 0, C_out, s));
@@ -1205,6 +1242,107 @@ int nmf_subtract(nmf_handle h, const float* H, const float* C, const float* T, c
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(prof_drain(h));
   return NMF_OK;
+}
+
+// ---------------------------------------------------------------------------
+int nmf_closest_frames(nmf_handle h, const float* V, const float* M, int64_t n, int64_t p,
+                       const float* T, const float* M_T, int64_t f, int64_t n_sel,
+                       double* dist_out, int32_t* idx_out, void* stream) {
+  if (!V || !M || !T || !M_T || !idx_out) return fail(NMF_ERR_ARG, "NULL array argument");
+  int rc = check_dims(n, p, "closest_frames");
+  if (rc || (rc = check_dims(f, p, "closest_frames"))) return rc;
+  if (n > 0x7fffffff || f > 65535) return fail(NMF_ERR_SHAPE, "n must fit in int32, f <= 65535");
+  if (n_sel < 1 || n_sel > n) return fail(NMF_ERR_ARG, "n_sel must be in [1, n]");
+  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+  DeviceGuard g(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  double* dist = dist_out;
+  int* stat;
+  if ((rc = ws(h, "stat", 1, &stat))) return rc;
+  if (!dist && (rc = ws(h, "cf.dist", (size_t)f * n, &dist))) return rc;
+  LAUNCH(NMF_K_OTHER, launch_set_int(stat, 0, s));
+  LAUNCH(NMF_K_OTHER, launch_frame_dist(T, M_T, V, M, (int)f, (int)n, p, dist, stat, s));
+  LAUNCH(NMF_K_OTHER, launch_select_rank(dist, (int)f, (int)n, (int)n_sel, idx_out, s));
+  int st = 0;
+  HIP_TRY(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(prof_drain(h));
+  if (st & 1) return fail(NMF_ERR_NONFINITE, "non-finite data under positive weight");
+  return NMF_OK;
+}
+
+int nmf_best_factor(nmf_handle h, const float* H, const float* C, const float* T,
+                    const float* M_T, const float* region, int64_t f, int64_t k, int64_t p,
+                    float s_lo, float s_hi, float* scale_out, void* stream) {
+  if (!H || !C || !T || !M_T || !scale_out) return fail(NMF_ERR_ARG, "NULL array argument");
+  int rc = check_dims(f, p, "best_factor");
+  if (rc) return rc;
+  if (k < 1 || k > 4096) return fail(NMF_ERR_ARG, "k must be in [1, 4096]");
+  if (f > 0x7fffffff) return fail(NMF_ERR_SHAPE, "too many frames");
+  if (!(s_lo <= s_hi) || std::isnan(s_lo) || std::isnan(s_hi))
+    return fail(NMF_ERR_ARG, "need s_lo <= s_hi");
+  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+  DeviceGuard g(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  LAUNCH(NMF_K_OTHER, launch_best_factor(H, C, T, M_T, region, f, (int)k, p, s_lo, s_hi,
+                                         scale_out, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(prof_drain(h));
+  return NMF_OK;
+}
+
+int nmf_build_basis_sequential(nmf_handle h, const float* V, const float* M, int64_t n, int64_t p,
+                               const nmf_params* prm, float* W_out, float* H_out,
+                               double* obj_stages, nmf_report* rep, void* stream) {
+  if (!V || !M || !W_out || !H_out) return fail(NMF_ERR_ARG, "NULL array argument");
+  int rc = check_dims(n, p, "build_basis_sequential");
+  if (rc) return rc;
+  if ((rc = check_params(prm, n, p, true))) return rc;
+  if (rep && rep->struct_size != sizeof(nmf_report))
+    return fail(NMF_ERR_ARG, "nmf_report.struct_size mismatch");
+  if (kp_for(prm->k) > KP_MAX) return fail(NMF_ERR_UNSUPPORTED, "k > 224 is not supported by this build");
+  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+  DeviceGuard g(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int K = prm->k;
+  float *I_W, *I_H, *B_W[2], *B_H[2];
+  if ((rc = ws(h, "seq.IW", (size_t)n * K, &I_W)) || (rc = ws(h, "seq.IH", (size_t)K * p, &I_H)) ||
+      (rc = ws(h, "seq.W0", (size_t)n * K, &B_W[0])) || (rc = ws(h, "seq.H0", (size_t)K * p, &B_H[0])) ||
+      (rc = ws(h, "seq.W1", (size_t)n * K, &B_W[1])) || (rc = ws(h, "seq.H1", (size_t)K * p, &B_H[1])))
+    return rc;
+  nmf_params sp = *prm;
+  sp.flags &= ~NMF_F_ASYNC;  // each stage's result is needed by the next one
+  const float *Wp = nullptr, *Hp = nullptr;
+  int64_t total_iters = 0;
+  float total_ms = 0.f;
+  int warn = 0, result = NMF_OK;
+  nmf_report sr{};
+  sr.struct_size = sizeof(nmf_report);
+  for (int j = 1; j <= K; ++j) {
+    float* Wo = j == K ? W_out : B_W[j & 1];
+    float* Ho = j == K ? H_out : B_H[j & 1];
+    LAUNCH(NMF_K_OTHER, launch_seq_start(Wp, Hp, n, p, j, K, prm->seed, I_W, I_H, s));
+    sp.k = j;
+    const int st = nmf_build_basis(h, V, M, n, p, &sp, I_W, I_H, Wo, Ho, nullptr, &sr, stream);
+    if (st < 0) return st;
+    if (st > 0) {
+      warn |= sr.status_flags;
+      if (result == NMF_OK || st == NMF_WARN_NONMONOTONE) result = st;
+    }
+    if (obj_stages) obj_stages[j - 1] = sr.objective;
+    total_iters += sr.iters_run;
+    total_ms += sr.elapsed_ms;
+    Wp = Wo;
+    Hp = Ho;
+  }
+  if (rep) {
+    rep->iters_run = (int32_t)std::min<int64_t>(total_iters, 0x7fffffff);
+    rep->status_flags = warn;
+    rep->objective = sr.objective;
+    rep->objective_rel = sr.objective_rel;
+    rep->elapsed_ms = total_ms;
+  }
+  return result;
 }
 
 int nmf_autotune_report(nmf_handle h, char* buf, size_t cap) {

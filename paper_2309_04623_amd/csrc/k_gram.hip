@@ -435,8 +435,82 @@ __global__ __launch_bounds__(1024) void k_frame_order(const int64_t* offsets, in
   for (int i = threadIdx.x; i < f; i += 1024) order[i] = vs[i];
 }
 
-hipError_t launch_frame_order(const int64_t* offsets, int f, int* order, hipStream_t s) {
-  if (f > MAX_SORT_FRAMES) return hipErrorInvalidValue;
+// More frames: a stable least-significant-digit radix sort (4-bit digits,
+// eight passes) of key = INT32_MAX - size with the frame index as value, in
+// one workgroup over global ping-pong buffers (tmp: 4 f ints).  Stability
+// keeps equal sizes in increasing index order, as the bitonic sort orders
+// them.  Thread t owns the contiguous element range [t C, (t+1) C).
+__global__ __launch_bounds__(1024) void k_frame_order_radix(const int64_t* offsets, int f,
+                                                           int* tmp, int* order) {
+  constexpr int NT = 1024, ND = 16;
+  __shared__ int cnt[ND * NT];  // digit-major: cnt[d * NT + t]
+  __shared__ int part[NT];
+  const int t = threadIdx.x;
+  const int C = (f + NT - 1) / NT;
+  const int b0 = min(t * C, f), b1 = min(b0 + C, f);
+  int* ka = tmp;
+  int* va = tmp + f;
+  int* kb = tmp + 2 * f;
+  int* vb = tmp + 3 * f;
+  for (int i = b0; i < b1; ++i) {
+    const int64_t d = offsets[i + 1] - offsets[i];
+    const int sz = d < 0 ? 0 : (d > 0x7fffffff ? 0x7fffffff : (int)d);
+    ka[i] = 0x7fffffff - sz;
+    va[i] = i;
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 8; ++pass) {
+    const int sh = 4 * pass;
+    int c[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) c[d] = 0;
+    for (int i = b0; i < b1; ++i) ++c[(ka[i] >> sh) & 15];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) cnt[d * NT + t] = c[d];
+    __syncthreads();
+    // exclusive scan of cnt in digit-major order: thread t owns entries
+    // [16 t, 16 t + 16)
+    int loc = 0;
+#pragma unroll
+    for (int q = 0; q < ND; ++q) loc += cnt[16 * t + q];
+    part[t] = loc;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {
+      const int v = t >= off ? part[t - off] : 0;
+      __syncthreads();
+      part[t] += v;
+      __syncthreads();
+    }
+    int run = part[t] - loc;
+#pragma unroll
+    for (int q = 0; q < ND; ++q) {
+      const int v = cnt[16 * t + q];
+      cnt[16 * t + q] = run;
+      run += v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < ND; ++d) c[d] = cnt[d * NT + t];
+    for (int i = b0; i < b1; ++i) {
+      const int k = ka[i];
+      const int pos = c[(k >> sh) & 15]++;
+      kb[pos] = k;
+      vb[pos] = va[i];
+    }
+    __syncthreads();
+    int* x = ka; ka = kb; kb = x;
+    x = va; va = vb; vb = x;
+  }
+  for (int i = b0; i < b1; ++i) order[i] = va[i];
+}
+
+hipError_t launch_frame_order(const int64_t* offsets, int f, int* order, int* tmp,
+                              hipStream_t s) {
+  if (f > MAX_SORT_FRAMES) {
+    if (!tmp) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_frame_order_radix, dim3(1), dim3(1024), 0, s, offsets, f, tmp, order);
+    return hipGetLastError();
+  }
   int n2 = 1;
   while (n2 < f) n2 <<= 1;
   hipLaunchKernelGGL(k_frame_order, dim3(1), dim3(1024), 0, s, offsets, f, n2, order);

@@ -71,6 +71,14 @@ enum DualMode { MODE_UPDATE = 0, MODE_SPLIT = 1, MODE_OBJ = 2 };
 hipError_t launch_dual(int prec, int kp, int mode, int nw, int pipe, const DualArgs& a, int grid_x,
                        int grid_y, hipStream_t s);
 
+// Wide-basis form of the same half-step (KP = 96..224): a workgroup of four
+// waves owns four adjacent column tiles (one per wave) and shares each row
+// tile's left-factor operand set through LDS.  grid = (wide_groups(C_pad /
+// 32), splits); the objective partials are indexed by workgroup and are
+// written in every mode when Jpart is set.
+int wide_groups(int col_tiles);
+hipError_t launch_wide(int prec, int kp, int mode, const DualArgs& a, int grid_y, hipStream_t s);
+
 // Finishes a split half-step: sums the partials in a fixed order, applies
 // the update to the factor (old value read from t, the KP x C_pad layout)
 // and refreshes every layout.  Optionally also sums the objective partials
@@ -207,9 +215,27 @@ struct GramArgs {
 size_t gram_lds_bytes(int K, int KP);
 hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, hipStream_t s,
                        int* grid_out);
-// Longest-first processing order of up to MAX_SORT_FRAMES CSR frames.
+// Longest-first processing order of CSR frames (equal sizes by index): a
+// bitonic sort in LDS up to MAX_SORT_FRAMES frames, a radix sort over
+// ``tmp`` (4 f ints of device scratch) beyond.
 constexpr int MAX_SORT_FRAMES = 8192;
-hipError_t launch_frame_order(const int64_t* offsets, int f, int* order, hipStream_t s);
+hipError_t launch_frame_order(const int64_t* offsets, int f, int* order, int* tmp,
+                              hipStream_t s);
+
+// ---- reference selection, best factor, sequential build --------------------
+// d[f, n] = sum over pixels valid in both of (T - V)^2 (FP32 per 64-pixel
+// chunk, FP64 across chunks); status |= 1 for non-finite data under weight.
+hipError_t launch_frame_dist(const float* T, const float* MT, const float* V, const float* M,
+                             int f, int n, int64_t p, double* dist, int* status, hipStream_t s);
+// idx[f, r] = reference of rank r < n_sel by (distance, index).
+hipError_t launch_select_rank(const double* dist, int f, int n, int n_sel, int32_t* idx,
+                              hipStream_t s);
+hipError_t launch_best_factor(const float* H, const float* C, const float* T, const float* MT,
+                              const float* region, int64_t f, int k, int64_t p, float s_lo,
+                              float s_hi, float* scale, hipStream_t s);
+// Start of stage j (of K) of the component-by-component build.
+hipError_t launch_seq_start(const float* Wp, const float* Hp, int64_t n, int64_t p, int j, int K,
+                            uint64_t seed, float* W0, float* H0, hipStream_t s);
 
 // ---- learned warm start ---------------------------------------------------
 enum { ACT_NONE = 0, ACT_GELU = 1 };

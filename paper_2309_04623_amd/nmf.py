@@ -83,6 +83,12 @@ _SIGS = {
     "nmf_warmstart_train": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32,
                                            _i32, ctypes.c_float, _u64, _dp, _vp]),
     "nmf_warmstart_infer": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]),
+    "nmf_closest_frames": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp, _vp, _i64, _i64, _vp,
+                                          _vp, _vp]),
+    "nmf_best_factor": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64,
+                                       ctypes.c_float, ctypes.c_float, _vp, _vp]),
+    "nmf_build_basis_sequential": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, ctypes.POINTER(Params),
+                                                  _vp, _vp, _dp, ctypes.POINTER(Report), _vp]),
     "nmf_autotune_report": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "nmf_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "nmf_profile_get": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int64),
@@ -293,6 +299,67 @@ def subtract(H, C, T, MT, scale=None, want_model=True, handle=None):
                               _dev_ptr(scale, "scale", f32), _dev_ptr(model, "model_out"),
                               _dev_ptr(resid, "resid_out"), _stream(dev)))
     return model, resid
+
+
+def closest_frames(V, M, T, MT, n_sel, want_dist=False, handle=None):
+    """Reference selection: per target frame, the indices (int32, f x n_sel)
+    of the n_sel library frames closest in the masked Euclidean norm, by
+    increasing distance (ties by index); optionally the f x n FP64
+    distances."""
+    torch = _torch()
+    dev = V.device.index or 0
+    h = handle or default_handle(dev)
+    n, p = V.shape
+    f = T.shape[0]
+    f32 = torch.float32
+    idx = torch.empty((f, n_sel), dtype=torch.int32, device=V.device)
+    dist = torch.empty((f, n), dtype=torch.float64, device=V.device) if want_dist else None
+    _check(lib().nmf_closest_frames(h.h, _dev_ptr(V, "V", f32), _dev_ptr(M, "M", f32), n, p,
+                                    _dev_ptr(T, "T", f32), _dev_ptr(MT, "M_T", f32), f, n_sel,
+                                    _dev_ptr(dist, "dist_out"), _dev_ptr(idx, "idx_out"),
+                                    _stream(dev)))
+    return (idx, dist) if want_dist else idx
+
+
+def best_factor(H, C, T, MT, region=None, s_lo=0.0, s_hi=float("inf"), handle=None):
+    """Per-frame scale of the model PSF minimising the residual variance
+    over the valid pixels (inside ``region`` when given), clamped."""
+    torch = _torch()
+    dev = H.device.index or 0
+    h = handle or default_handle(dev)
+    k, p = H.shape
+    f = T.shape[0]
+    f32 = torch.float32
+    out = torch.empty(f, dtype=f32, device=H.device)
+    _check(lib().nmf_best_factor(h.h, _dev_ptr(H, "H", f32), _dev_ptr(C, "C", f32),
+                                 _dev_ptr(T, "T", f32), _dev_ptr(MT, "M_T", f32),
+                                 _dev_ptr(region, "region", f32), f, k, p, s_lo, s_hi,
+                                 _dev_ptr(out, "scale_out"), _stream(dev)))
+    return out
+
+
+def build_basis_sequential(V, M, k, iters, *, precision="fp32", seed=0, flags=0, eps=1e-30,
+                           tol=0.0, check_every=0, handle=None):
+    """Component-by-component basis construction: stages 1..k, each
+    ``iters`` iterations from the previous components plus a new one.
+    Returns (W, H, objective after each stage, report)."""
+    torch = _torch()
+    dev = V.device.index or 0
+    h = handle or default_handle(dev)
+    n, p = V.shape
+    f32 = torch.float32
+    W = torch.empty((n, k), dtype=f32, device=V.device)
+    H = torch.empty((k, p), dtype=f32, device=V.device)
+    stages = np.zeros(k, np.float64)
+    prm = make_params(k, iters, precision, seed, flags, eps, 0, tol, check_every)
+    rep = _new_report()
+    st = _check(lib().nmf_build_basis_sequential(
+        h.h, _dev_ptr(V, "V", f32), _dev_ptr(M, "M", f32), n, p, ctypes.byref(prm),
+        _dev_ptr(W, "W_out"), _dev_ptr(H, "H_out"), stages.ctypes.data, ctypes.byref(rep),
+        _stream(dev)))
+    info = rep.as_dict()
+    info["status"] = st
+    return W, H, stages, info
 
 
 def profile_enable(handle: Handle, on: bool = True):

@@ -255,7 +255,8 @@ def make_ragged(H0: np.ndarray, ny: int, nx: int, frames: int, pmin: int, pmax: 
                 cfg: int = 4, binary: bool = True, peak: float = 1e6) -> RaggedFrames:
     """Frames that keep a compact region of P_f ~ U{pmin..pmax} pixels
     nearest the star outside the 4QPM-like cross (ties by flat index), drawn
-    as Poisson-like realisations of random non-negative mixtures of H0."""
+    as Poisson-like realisations of random non-negative mixtures of H0.
+    Pixels of a frame are stored in increasing index order."""
     p = ny * nx
     cross = mask_cross(ny, nx, 8.0, 2.0)
     _, _, r = radius_grid(ny, nx)
@@ -263,25 +264,36 @@ def make_ragged(H0: np.ndarray, ny: int, nx: int, frames: int, pmin: int, pmax: 
     order = order[cross[order]]
     pmax = min(pmax, order.size)
     pmin = min(pmin, pmax)
+    # rank of every valid pixel in the distance order, listed by pixel index:
+    # frame f keeps exactly the valid pixels of rank < P_f
+    valid = np.sort(order)
+    rank = np.empty(p, np.int64)
+    rank[order] = np.arange(order.size)
+    vrank = rank[valid]
     g = rng(cfg, S_SCIENCE)
     sizes = g.integers(pmin, pmax + 1, size=frames)
+    k0 = H0.shape[0]
+    ws = g.gamma(2.0, 1.0, size=(frames, k0))
     offsets = np.zeros(frames + 1, np.int64)
     offsets[1:] = np.cumsum(sizes)
     nnz = int(offsets[-1])
     pix = np.empty(nnz, np.int32)
     val = np.empty(nnz, np.float32)
     wt = np.empty(nnz, np.float32)
-    k0 = H0.shape[0]
-    for f in range(frames):
-        sel = np.sort(order[: sizes[f]])
-        w = g.gamma(2.0, 1.0, size=k0)
-        clean = w @ H0[:, sel]
-        gain = peak / clean.max()
-        v = g.poisson(gain * clean) / gain
-        s, e = offsets[f], offsets[f + 1]
-        pix[s:e] = sel
-        val[s:e] = v
-        wt[s:e] = 1.0 if binary else 1.0 / (v + 0.01)
+    Hv = np.ascontiguousarray(H0[:, valid])
+    chunk = 256
+    for c0 in range(0, frames, chunk):
+        clean_rows = ws[c0:c0 + chunk] @ Hv
+        for i, row in enumerate(clean_rows):
+            f = c0 + i
+            keep = vrank < sizes[f]
+            clean = row[keep]
+            gain = peak / clean.max()
+            v = g.poisson(gain * clean) / gain
+            s, e = offsets[f], offsets[f + 1]
+            pix[s:e] = valid[keep]
+            val[s:e] = v
+            wt[s:e] = 1.0 if binary else 1.0 / (v + 0.01)
     return RaggedFrames(offsets, pix, val, wt, p)
 
 

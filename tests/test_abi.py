@@ -18,7 +18,7 @@ EXPECTED = {
     "nmf_project_ragged", "nmf_subtract", "nmf_profile_enable", "nmf_profile_get",
     "nmf_device_clock_khz", "nmf_warmstart_param_count", "nmf_warmstart_init",
     "nmf_warmstart_pool", "nmf_warmstart_step", "nmf_warmstart_train", "nmf_warmstart_infer",
-    "nmf_autotune_report",
+    "nmf_autotune_report", "nmf_closest_frames", "nmf_best_factor", "nmf_build_basis_sequential",
 }
 
 
@@ -192,3 +192,39 @@ def test_warmstart_layout_and_validation(L):
     assert L.nmf_warmstart_train(None, FAKE, FAKE, FAKE, FAKE, FAKE, 100, 4, 0, 1, 8, 0.0, 0, None,
                                  None) == nmf.NMF_ERR_ARG
     assert L.nmf_warmstart_pool(None, FAKE, FAKE, 2, 0, 5, FAKE, FAKE, None) == nmf.NMF_ERR_SHAPE
+
+
+def test_pipeline_calls_validation(L):
+    """Reference selection, best factor and the sequential build reject bad
+    arguments on the host, before any device work."""
+    F = FAKE
+    # closest frames: n_sel out of range, null index output, handle
+    assert L.nmf_closest_frames(None, F, F + 4, 10, 100, F + 8, F + 12, 2, 0, None, F + 16,
+                                None) == nmf.NMF_ERR_ARG
+    assert L.nmf_closest_frames(None, F, F + 4, 10, 100, F + 8, F + 12, 2, 11, None, F + 16,
+                                None) == nmf.NMF_ERR_ARG
+    assert L.nmf_closest_frames(None, F, F + 4, 10, 100, F + 8, F + 12, 2, 3, None, None,
+                                None) == nmf.NMF_ERR_ARG
+    assert L.nmf_closest_frames(None, F, F + 4, 0, 100, F + 8, F + 12, 2, 3, None, F + 16,
+                                None) == nmf.NMF_ERR_SHAPE
+    assert L.nmf_closest_frames(None, F, F + 4, 10, 100, F + 8, F + 12, 2, 3, None, F + 16,
+                                None) == nmf.NMF_ERR_ARG
+    assert b"handle" in L.nmf_last_error()
+    # best factor: empty range, k out of range
+    assert L.nmf_best_factor(None, F, F + 4, F + 8, F + 12, None, 2, 3, 100, 2.0, 1.0, F + 16,
+                             None) == nmf.NMF_ERR_ARG
+    assert L.nmf_best_factor(None, F, F + 4, F + 8, F + 12, None, 2, 0, 100, 0.0, 1.0, F + 16,
+                             None) == nmf.NMF_ERR_ARG
+    assert L.nmf_best_factor(None, F, F + 4, F + 8, F + 12, None, 2, 3, 100, 0.0, 1.0, None,
+                             None) == nmf.NMF_ERR_ARG
+    # sequential build: k above the supported width, k > min(n, p)
+    prm = _prm(L, k=225)
+    assert L.nmf_build_basis_sequential(None, F, F + 4, 300, 1000, ctypes.byref(prm), F + 8,
+                                        F + 12, None, None, None) == nmf.NMF_ERR_UNSUPPORTED
+    prm = _prm(L, k=40)
+    assert L.nmf_build_basis_sequential(None, F, F + 4, 30, 1000, ctypes.byref(prm), F + 8,
+                                        F + 12, None, None, None) == nmf.NMF_ERR_ARG
+    prm = _prm(L, k=4)
+    assert L.nmf_build_basis_sequential(None, F, F + 4, 30, 1000, ctypes.byref(prm), F + 8,
+                                        F + 12, None, None, None) == nmf.NMF_ERR_ARG
+    assert b"handle" in L.nmf_last_error()

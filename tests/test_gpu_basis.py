@@ -8,8 +8,8 @@ initialisation,
   * relative model error ||M o (W_gpu H_gpu - W_o H_o)|| / ||M o W_o H_o||
     <= 1e-4 (FP32);
   * the GPU's own FP64-accumulated J history within 1e-5 of the oracle's.
-The split-precision path (bf16x3) is held to 1e-4 on the objective and 1e-3
-on the model; its measured errors are printed.
+The split-precision path (bf16x3) is held to the same bars; its measured
+errors are printed.
 """
 import numpy as np
 import pytest
@@ -20,7 +20,7 @@ from tests.helpers import dev, host, objective64, random_problem, rel_model_err,
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": (1e-5, 1e-4), "bf16x3": (1e-4, 1e-3)}
+TOL = {"fp32": (1e-5, 1e-4), "bf16x3": (1e-5, 1e-4)}
 
 
 def _check_run(V, M, k, iters, precision, seed=7, tag="", flags=0):
@@ -79,10 +79,13 @@ def test_cfg1_parity(precision):
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("n,p,k,iters", [(37, 1000, 5, 60), (70, 333, 30, 40), (33, 2050, 33, 30),
-                                         (130, 700, 100, 20), (200, 1057, 64, 25)])
+                                         (150, 900, 90, 20), (130, 700, 100, 20),
+                                         (200, 1057, 64, 25), (230, 1100, 150, 12),
+                                         (210, 700, 180, 10), (260, 800, 200, 10)])
 def test_ragged_shapes_parity(n, p, k, iters, precision):
     """Shapes that span several tiles with ragged tails in both directions and
-    every padded component count (32, 64, 96, 128)."""
+    every padded component count (32 ... 224); from 96 on the wide-basis
+    kernel runs, with column groups whose last waves have no tile."""
     V, M = random_problem(n * 7 + p, n, p, k)
     _check_run(V, M, k, iters, precision, tag="ragged")
 
@@ -99,6 +102,15 @@ def test_binary_weights_parity():
     _check_run(lib.V, lib.M, 16, 60, "fp32", tag="cfg3-reduced")
     _check_run(lib.V, lib.M, 16, 60, "bf16x3", tag="cfg3-reduced")
     _check_run(lib.V, lib.M, 16, 60, "fp32", tag="cfg3-reduced bitmask",
+               flags=nmf.F_BINARY_WEIGHTS)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_binary_weights_wide_basis_parity(precision):
+    """MIRI-like binary-weight library with a wide basis (K = 100, the
+    precision-study component count) from bitmask weights."""
+    lib = synth.make_cfg3(n=160, ny=56, nx=72, k0=120, frames=1)
+    _check_run(lib.V, lib.M, 100, 25, precision, tag="cfg3-reduced wide bitmask",
                flags=nmf.F_BINARY_WEIGHTS)
 
 
@@ -224,7 +236,7 @@ def test_data_errors_and_guards():
     assert np.array_equal(host(W)[11], host(W0)[11])
 
 
-@pytest.mark.parametrize("c,tol", [(10, 1e-4), (7, 3e-4), (25, 1e-5)])
+@pytest.mark.parametrize("c,tol", [(10, 1e-4), (7, 3e-4), (25, 3e-5)])
 def test_tolerance_stop_matches_oracle_rule(c, tol):
     """The on-device stop rule (relative decrease of J over c iterations,
     tested at multiples of c; the iteration at which it passes is the last)

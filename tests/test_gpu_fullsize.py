@@ -1,0 +1,105 @@
+"""Full-size basis-build parity against stored FP64 oracle runs.
+
+The FP64 oracle needs minutes to hours for the full-size libraries, so it
+ran once on the CPU (``tests/golden/make_oracle_fixtures.py``, which calls
+only ``oracle/``) and its expected values are stored: the Eq. 2 objective
+before every iteration, and at checkpoints the oracle's W on a fixed random
+subset of rows and H on a fixed random subset of pixel columns, so that its
+model W H is known on that block.
+
+The GPU runs the same iterations from the same seeded start, chained over the
+checkpoints (the iteration is memoryless, so a run resumed from its own
+factors continues it exactly).  Bars, in both precision forms:
+  * relative objective |J(W_gpu, H_gpu) - J_oracle| / J_oracle <= 1e-5 after
+    the last iteration, J of the GPU factors evaluated in FP64 on the host;
+  * the GPU's own FP64 objective history within 1e-5 of the oracle's at
+    every iteration (the drift is printed every 100 iterations);
+  * relative model error ||M o (W_gpu H_gpu - W_o H_o)|| / ||M o W_o H_o||
+    <= 1e-4 on the sampled block at every checkpoint;
+  * elementwise, |W_gpu H_gpu - W_o H_o| / (|W_o H_o| + 1e-3 rms) at the
+    unmasked pixels of the block <= 1e-3 (a per-pixel bound that norm-based
+    checks cannot give; the floor keeps near-zero model pixels from
+    dominating).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2309_04623_amd import nmf, synth
+from tests.helpers import dev, host, objective64, say
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _fixture(name):
+    path = os.path.join(GOLDEN, f"oracle_{name}_fullsize.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"stored oracle run {path} not present")
+    return np.load(path)
+
+
+def _run(lib, z, precision, flags):
+    import hashlib
+    sha = lambda x: hashlib.sha256(np.ascontiguousarray(x, np.float32).tobytes()).hexdigest()
+    assert sha(lib.V) == str(z["v_sha"]) and sha(lib.M) == str(z["m_sha"]), \
+        "the generator no longer draws the library the oracle ran on"
+    k, seed = int(z["k"]), int(z["seed"])
+    rows, cols = z["rows"], z["cols"]
+    V, M = dev(lib.V), dev(lib.M)
+    Mblk = lib.M[np.ix_(rows, cols)].astype(np.float64)
+    J_all = []
+    W = H = None
+    t = 0
+    for c, ck in enumerate(z["ck_iters"]):
+        ck = int(ck)
+        say("fullsize", precision, f"iterations {t}..{ck}")
+        W, H, J, rep = nmf.build_basis(V, M, k, ck - t, precision=precision, seed=seed,
+                                       W_init=W, H_init=H, flags=flags)
+        J_all.extend(J[:-1])  # J[0] repeats the previous chunk's last value
+        last_J = J[-1]
+        t = ck
+        Wg, Hg = host(W), host(H)
+        Yg = Wg[rows] @ Hg[:, cols]
+        Yo = z["W_ck"][c].astype(np.float64) @ z["H_ck"][c].astype(np.float64)
+        model = np.linalg.norm(Mblk * (Yg - Yo)) / np.linalg.norm(Mblk * Yo)
+        on = Mblk > 0
+        floor = 1e-3 * np.sqrt(np.mean(Yo[on] ** 2))
+        elem = np.max(np.abs(Yg - Yo)[on] / (np.abs(Yo[on]) + floor))
+        print(f"  t={t}: model={model:.3e} elementwise={elem:.3e}", flush=True)
+        assert model <= 1e-4, (t, model)
+        assert elem <= 1e-3, (t, elem)
+    J_all.append(last_J)
+    J_all = np.array(J_all)
+    Jo = z["J"]
+    assert J_all.shape == Jo.shape
+    drift = np.abs(J_all - Jo) / Jo
+    print("  J drift every 100 iterations: " +
+          " ".join(f"{i}:{drift[i]:.1e}" for i in range(0, len(drift), 100)), flush=True)
+    assert drift.max() <= 1e-5, drift.max()
+    J64 = objective64(lib.V, lib.M, Wg, Hg)
+    relJ = abs(J64 - Jo[-1]) / Jo[-1]
+    print(f"  relJ={relJ:.3e} (max history drift {drift.max():.3e})", flush=True)
+    assert relJ <= 1e-5
+    assert np.all(Wg >= 0) and np.all(Hg >= 0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_stis_fullsize_1000_iterations(precision):
+    """STIS-shaped library at full size: 500 images of 200x200 px, K = 30,
+    1000 iterations, weights mask / (V + 0.01)."""
+    z = _fixture("stis")
+    lib = synth.make_cfg2(frames=1)
+    _run(lib, z, precision, 0)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_miri_fullsize_500_iterations(precision):
+    """MIRI-shaped precision study at full size: 2000 images of 224x288 px,
+    K = 100, 500 iterations, binary weights stored as bitmasks."""
+    z = _fixture("miri")
+    lib = synth.make_cfg3(frames=1)
+    _run(lib, z, precision, nmf.F_BINARY_WEIGHTS)

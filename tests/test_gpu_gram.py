@@ -188,3 +188,27 @@ def test_cfg4_shaped_batch_sample():
         co = nmf64.project_ragged(sub_off, rf.pix[sl], rf.val[sl], rf.wt[sl], H, C0[i:i + 1], 300)
         T, MT = nmf64.ragged_to_dense(sub_off, rf.pix[sl], rf.val[sl], rf.wt[sl], ny * nx)
         _compare(T, MT, H, Cg[i:i + 1], co, derived=True)
+
+
+def test_ragged_many_frames_longest_first_order_is_a_permutation():
+    """More frames than the in-LDS sort takes (9000 > 8192): the longest-first
+    order comes from the radix sort; every frame is processed exactly once
+    (a frame skipped or processed twice would leave or clobber its
+    coefficients), so every frame matches the oracle."""
+    k, p = 4, 300
+    H = _basis(k, p, seed=3)
+    g = np.random.default_rng(4)
+    sizes = g.integers(1, p + 1, 9000)
+    offs, pix, val, wt = _ragged(H, sizes, seed=5, binary=True)
+    f = len(sizes)
+    iters = 30
+    C0 = prng.init_matrix(11, prng.MAT_C, f, k)
+    say("ragged 9000 frames")
+    C, ticks, _ = nmf.project_ragged(dev(H), dev_i64(offs), dev_i32(pix), dev(val), None, iters,
+                                     seed=11, want_ticks=True)
+    Cg = host(C)
+    Co = nmf64.project_ragged(offs, pix, val, wt, H, C0, iters)
+    scale = np.maximum(np.abs(Co).max(axis=1, keepdims=True), 1e-30)
+    assert np.max(np.abs(Cg - Co) / scale) < 1e-4
+    t = host(ticks).astype(np.int64).reshape(f, 2)
+    assert np.all(t[:, 0] > 0) and np.all(t[:, 1] >= t[:, 0])

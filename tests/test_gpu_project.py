@@ -59,10 +59,9 @@ def _projection_case(f, k, p, iters, precision, peak):
                                          (3, 100, 3000, 80), (70, 33, 777, 120)])
 def test_projection_parity(f, k, p, iters, precision):
     """Photon-noise frames (peak 1e4 counts): relative objective <= 1e-5 and
-    model error <= 1e-4 (FP32); bf16x3 <= 1e-4 / 1e-3."""
+    model error <= 1e-4 in both precision forms."""
     relJ, model, _ = _projection_case(f, k, p, iters, precision, peak=1e4)
-    tol_j, tol_m = (1e-5, 1e-4) if precision == "fp32" else (1e-4, 1e-3)
-    assert relJ.max() <= tol_j and model.max() <= tol_m
+    assert relJ.max() <= 1e-5 and model.max() <= 1e-4
 
 
 @pytest.mark.parametrize("f,k,p,iters", [(50, 30, 6400, 300), (70, 33, 777, 120)])
