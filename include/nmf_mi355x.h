@@ -263,6 +263,23 @@ int nmf_closest_frames(nmf_handle h, const float* V, const float* M, int64_t n, 
                        const float* T, const float* M_T, int64_t f, int64_t n_sel,
                        double* dist_out, int32_t* idx_out, void* stream);
 
+/* ---- reference selection without allocation ---------------------------------
+ * For callers that cannot allocate device memory during the call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * nmf_closest_frames without the distance output, with every intermediate
+ * in a fixed per-device scratch array of 16 MiB that the library holds from
+ * the first nmf_create on the device until the process ends.  The call
+ * allocates nothing (no hipMalloc / hipFree, no workspace growth).
+ *   idx_out: f x n_sel int32 (device), as nmf_closest_frames.
+ * Limit: f * n <= 2,097,120 distances, else NMF_ERR_UNSUPPORTED (checked on
+ * the host before any work).  All calls on one GPU share that GPU's array,
+ * which keeps the last call's contents: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ * Synchronous.  Errors as nmf_closest_frames.                              */
+int nmf_closest_frames_noalloc(nmf_handle h, const float* V, const float* M, int64_t n,
+                               int64_t p, const float* T, const float* M_T, int64_t f,
+                               int64_t n_sel, int32_t* idx_out, void* stream);
+
 /* ---- best factor -------------------------------------------------------------
  * Sec. 2 and Sec. 4.1 (best factor finding, after Ren et al. 2018, which
  * the paper cites without restating): the per-frame scale s_f of the model

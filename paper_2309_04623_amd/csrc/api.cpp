@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -32,6 +33,21 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+}  // namespace
+
+// Scratch memory of the allocation-free entry point (nmf_closest_frames_noalloc):
+// a file-scope device array, one copy per GPU the library runs on, held
+// until the process ends.  Host code never uses the array's name as an
+// address: each device's copy is located once with hipGetSymbolAddress (at
+// the first nmf_create on that device) and only that address is used.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(16) << 20;
+constexpr size_t NOALLOC_STATUS_BYTES = 256;  // status word, then the distances
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
 }  // namespace
 
 struct nmf_handle_s {
@@ -380,6 +396,23 @@ int nmf_create(int hip_device, nmf_handle* out) {
       hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
     delete h;
     return fail(NMF_ERR_HIP, "hipEventCreate/hipStreamCreate failed");
+  }
+  if (hip_device < MAX_DEVICES) {
+    // once per device, with that device current: the address of this
+    // device's copy of the scratch array
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[hip_device]) {
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        (void)hipStreamDestroy(h->cap);
+        (void)hipEventDestroy(h->ev0);
+        (void)hipEventDestroy(h->ev1);
+        delete h;
+        return fail(NMF_ERR_HIP, "hipGetSymbolAddress of the scratch array failed");
+      }
+      g_scratch_ptr[hip_device] = ptr;
+    }
   }
   *out = h;
   return NMF_OK;
@@ -1267,6 +1300,38 @@ int nmf_closest_frames(nmf_handle h, const float* V, const float* M, int64_t n, 
   HIP_TRY(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(prof_drain(h));
+  if (st & 1) return fail(NMF_ERR_NONFINITE, "non-finite data under positive weight");
+  return NMF_OK;
+}
+
+int nmf_closest_frames_noalloc(nmf_handle h, const float* V, const float* M, int64_t n,
+                               int64_t p, const float* T, const float* M_T, int64_t f,
+                               int64_t n_sel, int32_t* idx_out, void* stream) {
+  if (!V || !M || !T || !M_T || !idx_out) return fail(NMF_ERR_ARG, "NULL array argument");
+  int rc = check_dims(n, p, "closest_frames_noalloc");
+  if (rc || (rc = check_dims(f, p, "closest_frames_noalloc"))) return rc;
+  if (n > 0x7fffffff || f > 65535) return fail(NMF_ERR_SHAPE, "n must fit in int32, f <= 65535");
+  if (n_sel < 1 || n_sel > n) return fail(NMF_ERR_ARG, "n_sel must be in [1, n]");
+  if ((uint64_t)f * (uint64_t)n > (NOALLOC_SCRATCH_BYTES - NOALLOC_STATUS_BYTES) / sizeof(double))
+    return fail(NMF_ERR_UNSUPPORTED, "f * n exceeds the scratch capacity of " +
+                                         std::to_string((NOALLOC_SCRATCH_BYTES - NOALLOC_STATUS_BYTES) /
+                                                        sizeof(double)) +
+                                         " distances");
+  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+  if (h->device >= MAX_DEVICES || !g_scratch_ptr[h->device])
+    return fail(NMF_ERR_UNSUPPORTED, "no scratch array on this device");
+  DeviceGuard g(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* base = static_cast<unsigned char*>(g_scratch_ptr[h->device]);
+  int* stat = reinterpret_cast<int*>(base);
+  double* dist = reinterpret_cast<double*>(base + NOALLOC_STATUS_BYTES);
+  // the array keeps the previous call's contents: the status word starts at 0
+  HIP_TRY(launch_set_int(stat, 0, s));
+  HIP_TRY(launch_frame_dist(T, M_T, V, M, (int)f, (int)n, p, dist, stat, s));
+  HIP_TRY(launch_select_rank(dist, (int)f, (int)n, (int)n_sel, idx_out, s));
+  int st = 0;
+  HIP_TRY(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
   if (st & 1) return fail(NMF_ERR_NONFINITE, "non-finite data under positive weight");
   return NMF_OK;
 }

@@ -85,6 +85,8 @@ _SIGS = {
     "nmf_warmstart_infer": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]),
     "nmf_closest_frames": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp, _vp, _i64, _i64, _vp,
                                           _vp, _vp]),
+    "nmf_closest_frames_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp, _vp, _i64,
+                                                  _i64, _vp, _vp]),
     "nmf_best_factor": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64,
                                        ctypes.c_float, ctypes.c_float, _vp, _vp]),
     "nmf_build_basis_sequential": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, ctypes.POINTER(Params),
@@ -319,6 +321,25 @@ def closest_frames(V, M, T, MT, n_sel, want_dist=False, handle=None):
                                     _dev_ptr(dist, "dist_out"), _dev_ptr(idx, "idx_out"),
                                     _stream(dev)))
     return (idx, dist) if want_dist else idx
+
+
+def closest_frames_noalloc(V, M, T, MT, n_sel, idx_out=None, handle=None):
+    """The same selection through the allocation-free entry point (every
+    intermediate in the library's fixed per-device scratch array); the
+    caller may pass the output tensor."""
+    torch = _torch()
+    dev = V.device.index or 0
+    h = handle or default_handle(dev)
+    n, p = V.shape
+    f = T.shape[0]
+    f32 = torch.float32
+    idx = idx_out if idx_out is not None else torch.empty((f, n_sel), dtype=torch.int32,
+                                                          device=V.device)
+    _check(lib().nmf_closest_frames_noalloc(h.h, _dev_ptr(V, "V", f32), _dev_ptr(M, "M", f32), n,
+                                            p, _dev_ptr(T, "T", f32), _dev_ptr(MT, "M_T", f32), f,
+                                            n_sel, _dev_ptr(idx, "idx_out", torch.int32),
+                                            _stream(dev)))
+    return idx
 
 
 def best_factor(H, C, T, MT, region=None, s_lo=0.0, s_hi=float("inf"), handle=None):
