@@ -97,8 +97,11 @@ typedef struct {
                             fused passes take k <= 224, the masked-Gram
                             projection k <= 200 (else NMF_ERR_UNSUPPORTED) */
   int32_t max_iter;      /* iterations of Eq. 3 (fixed count when tol == 0)   */
-  int32_t check_every;   /* objective test cadence for tol (0 = never)        */
-  double tol;            /* stop when (J[t-c] - J[t]) / J[t-c] < tol          */
+  int32_t check_every;   /* stop-rule test cadence c for tol (0 = never)      */
+  double tol;            /* stop rule, on when tol > 0 and check_every > 0:
+                            basis build: (J[t-c] - J[t]) / J[t-c] < tol;
+                            masked-Gram projection: per frame, the model
+                            change since the last test, relative (below) */
   uint64_t seed;         /* seed of the counter-based U(0,1) init             */
   int32_t precision;     /* enum nmf_precision                                */
   int32_t flags;         /* OR of enum nmf_flags                              */
@@ -198,7 +201,16 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
  * NMF_F_WARM_START (masked-Gram form only, C_init required): per frame, the
  * start with the lower objective of C_init and the seeded cold start is
  * used; rep->status_flags gets bit NMF_RS_WARM_FALLBACK when any frame fell
- * back, and nmf_warm_fallbacks() returns how many did.                    */
+ * back, and nmf_warm_fallbacks() returns how many did.
+ * Per-frame stop rule (masked-Gram form; Sec. 2 leaves the test open), on
+ * when tol > 0 and check_every = c > 0: before iteration t + 1, t = c, 2c,
+ * ..., a frame stops after t iterations when d G_f d^T <= tol^2 c_f G_f
+ * c_f^T, d = c_f - (c_f at the previous test, or the start at t = c), the
+ * weighted squared norm of the model change against that of the model.  A
+ * kept warm start that has not stopped by max_iter restarts from the cold
+ * start with the same cap (it then counts as fallen back).  Iterations per
+ * frame: nmf_frame_iters(); rep->iters_run is their maximum; a frame that
+ * never met the rule makes the call return NMF_WARN_MAXITER.              */
 int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float* T,
                 const float* M_T, int64_t f, const nmf_params* prm, const float* C_init,
                 float* C_out, double* obj_out, nmf_report* rep, void* stream);
@@ -229,6 +241,13 @@ int nmf_project_ragged(nmf_handle h, const float* H, int64_t k, int64_t p, int64
 /* Frames of the last synchronous warm-started projection on h that fell back
  * to the cold start (-1 if none ran). */
 int64_t nmf_warm_fallbacks(nmf_handle h);
+
+/* Iterations each frame ran in the last synchronous masked-Gram projection
+ * on h that had a stop rule.  iters_out: [host] room for f int32, or NULL to
+ * ask for the count only.  Returns that call's frame count (written unless
+ * iters_out is NULL), 0 when the last projection had no stop rule (or none
+ * ran), NMF_ERR_ARG when f is smaller than the count. */
+int64_t nmf_frame_iters(nmf_handle h, int32_t* iters_out, int64_t f);
 
 /* Frequency (kHz) of the device clock used by frame_ticks. */
 double nmf_device_clock_khz(nmf_handle h);

@@ -77,6 +77,7 @@ struct nmf_handle_s {
   };
   std::unordered_map<std::string, Tuned> tuned;
   int64_t last_fallbacks = -1;  // frames of the last warm start that fell back
+  std::vector<int32_t> last_frame_iters;  // of the last Gram projection with a stop rule
 };
 
 namespace {
@@ -712,6 +713,10 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   if (warm && !c.C_init) return fail(NMF_ERR_ARG, "NMF_F_WARM_START needs C_init");
   int* fb = nullptr;
   if (warm && (rc = ws(h, "gfallback", (size_t)c.f, &fb))) return rc;
+  // per-frame stop rule: on when tol > 0 and check_every > 0
+  const int ce = (c.prm->tol > 0.0 && c.prm->check_every > 0) ? c.prm->check_every : 0;
+  int* its = nullptr;
+  if (ce && (rc = ws(h, "giters", (size_t)c.f, &its))) return rc;
   GramArgs a{};
   a.HT = Hf.m;
   a.K = K;
@@ -737,6 +742,10 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   a.ticks = c.ticks;
   a.warm = warm ? 1 : 0;
   a.fallback = fb;
+  a.prec = c.prm->precision;
+  a.check_every = ce;
+  a.tol2 = ce ? c.prm->tol * c.prm->tol : 0.0;
+  a.iters_out = its;
   const FactorFillArgs fa = fill_args(Hf, c.H, 1, 0, 1, K);
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     hipError_t e;
@@ -755,8 +764,11 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
               (uint64_t)c.MT, (uint64_t)c.offsets, (uint64_t)c.nnz, (uint64_t)c.pix,
               (uint64_t)c.val, (uint64_t)c.wt, (uint64_t)c.C_init, (uint64_t)c.C_out,
               (uint64_t)c.ticks, (uint64_t)c.prm->seed, (uint64_t)c.prm->max_iter,
-              (uint64_t)c.prm->flags, (uint64_t)__builtin_bit_cast(uint32_t, c.prm->floor_eps),
-              (uint64_t)Hf.m, (uint64_t)queue, (uint64_t)stat, (uint64_t)order, (uint64_t)sort_tmp, (uint64_t)fb});
+              (uint64_t)c.prm->flags, (uint64_t)c.prm->precision,
+              (uint64_t)__builtin_bit_cast(uint32_t, c.prm->floor_eps), (uint64_t)ce,
+              __builtin_bit_cast(uint64_t, a.tol2), (uint64_t)its, (uint64_t)Hf.m,
+              (uint64_t)queue, (uint64_t)stat, (uint64_t)order, (uint64_t)sort_tmp,
+              (uint64_t)fb});
   HIP_TRY(hipEventRecord(h->ev0, s));
   HIP_TRY(run_graph(h, key, s, enqueue));
   HIP_TRY(hipEventRecord(h->ev1, s));
@@ -767,11 +779,29 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   HIP_TRY(prof_drain(h));
   if (st & 16) return fail(NMF_ERR_ARG, "CSR offsets or pixel indices out of range");
   int64_t nfb = 0;
+  std::vector<int> hfb;
   if (warm) {
-    std::vector<int> hfb((size_t)c.f);
+    hfb.resize((size_t)c.f);
     HIP_TRY(hipMemcpy(hfb.data(), fb, (size_t)c.f * sizeof(int), hipMemcpyDeviceToHost));
-    for (int v : hfb) nfb += v;
+    for (int v : hfb) nfb += v != 0;
     h->last_fallbacks = nfb;
+  }
+  // With a stop rule: iterations per frame (a warm start restarted cold
+  // counts both runs); a frame that ran to the cap of its last run did not
+  // meet the rule.
+  int iters_run = c.prm->max_iter, unmet = 0;
+  h->last_frame_iters.clear();
+  if (ce) {
+    h->last_frame_iters.resize((size_t)c.f);
+    HIP_TRY(hipMemcpy(h->last_frame_iters.data(), its, (size_t)c.f * sizeof(int),
+                      hipMemcpyDeviceToHost));
+    iters_run = 0;
+    for (int64_t i = 0; i < c.f; ++i) {
+      const int t = h->last_frame_iters[(size_t)i];
+      const int runs = (warm && hfb[(size_t)i] == 2) ? 2 : 1;
+      iters_run = std::max(iters_run, t);
+      unmet += t == runs * c.prm->max_iter;
+    }
   }
   if (c.prm->flags & NMF_F_VALIDATE_DATA) {
     if ((rc = status_from_stage(st))) return rc;
@@ -781,13 +811,13 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   if (rep) {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
-    rep->iters_run = c.prm->max_iter;
-    rep->status_flags = nfb > 0 ? NMF_RS_WARM_FALLBACK : 0;
+    rep->iters_run = iters_run;
+    rep->status_flags = (nfb > 0 ? NMF_RS_WARM_FALLBACK : 0) | (unmet ? 1 << NMF_WARN_MAXITER : 0);
     rep->objective = 0.0;
     rep->objective_rel = 0.0;
     rep->elapsed_ms = ms;
   }
-  return NMF_OK;
+  return unmet ? NMF_WARN_MAXITER : NMF_OK;
 }
 
 }  // namespace
@@ -1132,6 +1162,8 @@ int nmf_project(nmf_handle h, const float* H, int64_t k, int64_t p, const float*
   }
   if (prm->flags & NMF_F_WARM_START)
     return fail(NMF_ERR_UNSUPPORTED, "NMF_F_WARM_START needs the masked-Gram form");
+  if (prm->tol > 0.0 && prm->check_every > 0)
+    return fail(NMF_ERR_UNSUPPORTED, "the projection stop rule needs the masked-Gram form");
   if (KP > KP_MAX) return fail(NMF_ERR_UNSUPPORTED, "k > 224 is not supported by this build");
   if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
   const int prec = prm->precision;
@@ -1222,8 +1254,6 @@ int nmf_project_ragged(nmf_handle h, const float* H, int64_t k, int64_t p, int64
   if (prm->k != k) return fail(NMF_ERR_ARG, "params.k must equal k");
   if (k > p) return fail(NMF_ERR_ARG, "k must not exceed p");
   if (k > GRAM_K_MAX) return fail(NMF_ERR_UNSUPPORTED, "ragged projection needs k <= 200");
-  if (prm->precision != NMF_PREC_FP32)
-    return fail(NMF_ERR_UNSUPPORTED, "ragged projection runs FP32 products in this build");
   if (rep && rep->struct_size != sizeof(nmf_report))
     return fail(NMF_ERR_ARG, "nmf_report.struct_size mismatch");
   if ((const float*)C_out == H || (const float*)C_out == val || (const float*)C_out == wt)
@@ -1247,6 +1277,15 @@ int nmf_project_ragged(nmf_handle h, const float* H, int64_t k, int64_t p, int64
 }
 
 int64_t nmf_warm_fallbacks(nmf_handle h) { return h ? h->last_fallbacks : -1; }
+
+int64_t nmf_frame_iters(nmf_handle h, int32_t* iters_out, int64_t f) {
+  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+  const int64_t have = (int64_t)h->last_frame_iters.size();
+  if (!have || !iters_out) return have;
+  if (f < have) return fail(NMF_ERR_ARG, "iters_out must hold every frame");
+  std::copy(h->last_frame_iters.begin(), h->last_frame_iters.end(), iters_out);
+  return have;
+}
 
 double nmf_device_clock_khz(nmf_handle h) {
   if (!h) return 0.0;

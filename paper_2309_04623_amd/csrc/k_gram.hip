@@ -13,6 +13,12 @@
 //      iterations c_j <- max(c_j b_j / (c G)_j, eps) with c in LDS.
 // Pixels appear only through the staged chunks, so dense frames (all
 // pixels, weight row of M_T) and CSR frames share the kernel.
+//
+// G tiles take FP32 products (v_mfma_f32_32x32x2_f32 on the staged rows) or
+// split-precision ones: the chunk is also staged transposed (component
+// rows, pixels along the row) as bf16 hi/lo pairs of H and of H o m, so
+// that every operand of v_mfma_f32_32x32x16_bf16 is one 16-byte LDS read;
+// each tile then takes two reduction steps of three products per chunk.
 
 #include <type_traits>
 
@@ -41,7 +47,16 @@ __host__ __device__ constexpr int gram_waves() {
   return KP <= 128 ? 4 : 8;
 }
 
-template <int KP, bool RAGGED>
+// Transposed bf16 staging: a row per component, 16 dwords (32 pixels) used
+// of GT_STRIDE (the pad keeps the per-lane 16-byte reads conflict-free).
+constexpr int GT_STRIDE = 20;
+
+template <int KP>
+__host__ __device__ constexpr int gram_stage_floats(int prec) {
+  return 32 * KP + 64 + (prec == PREC_BF16X3 ? 4 * KP * GT_STRIDE : 0);
+}
+
+template <int KP, bool RAGGED, int PREC>
 __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   extern __shared__ __align__(16) float lds[];
   __shared__ int qslot;
@@ -57,8 +72,13 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   float* Hs = lds;            // [32][KP] gathered H^T rows
   float* ms = lds + 32 * KP;  // [32] weights
   float* ts = ms + 32;        // [32] data
+  // bf16 hi/lo of H^T and (H o m)^T, [KP][GT_STRIDE] dwords (2 pixels each)
+  uint32_t* hT_hi = reinterpret_cast<uint32_t*>(lds + 32 * KP + 64);
+  uint32_t* hT_lo = hT_hi + KP * GT_STRIDE;
+  uint32_t* hmT_hi = hT_lo + KP * GT_STRIDE;
+  uint32_t* hmT_lo = hmT_hi + KP * GT_STRIDE;
   float* G = lds;             // [K][K] after the pixel loop (aliases the above)
-  const int goff = (max(K * K, 32 * KP + 64) + 3) & ~3;
+  const int goff = (max(K * K, gram_stage_floats<KP>(PREC)) + 3) & ~3;
   double* bsh = reinterpret_cast<double*>(lds + goff);  // [KP]
   float* csh = reinterpret_cast<float*>(bsh + KP);      // [KP]
 
@@ -179,17 +199,53 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
         ts[tid] = t;
       }
       __syncthreads();
+      if constexpr (PREC == PREC_BF16X3) {
+        // transposed split staging: thread -> (component, pixel pair); the
+        // reads of Hs are consecutive across threads, the dword writes land
+        // in distinct banks (odd multiples of the row stride apart)
+        for (int x = tid; x < 16 * KP; x += NTH) {
+          const int comp = x % KP, pp = x / KP;
+          const float h0 = Hs[(2 * pp) * KP + comp], h1 = Hs[(2 * pp + 1) * KP + comp];
+          const float w0 = h0 * ms[2 * pp], w1 = h1 * ms[2 * pp + 1];
+          const f32x2 hv = {h0, h1}, wv = {w0, w1};
+          const bf16x2 hh = __builtin_convertvector(hv, bf16x2);
+          const bf16x2 hl = __builtin_convertvector(hv - __builtin_convertvector(hh, f32x2), bf16x2);
+          const bf16x2 wh = __builtin_convertvector(wv, bf16x2);
+          const bf16x2 wl = __builtin_convertvector(wv - __builtin_convertvector(wh, f32x2), bf16x2);
+          const int o = comp * GT_STRIDE + pp;
+          hT_hi[o] = __builtin_bit_cast(uint32_t, hh);
+          hT_lo[o] = __builtin_bit_cast(uint32_t, hl);
+          hmT_hi[o] = __builtin_bit_cast(uint32_t, wh);
+          hmT_lo[o] = __builtin_bit_cast(uint32_t, wl);
+        }
+        __syncthreads();
+      }
 
       // ---- G tiles: G[mi-block, mj-block] += (H o m) H^T over the chunk ---
 #pragma unroll
       for (int q = 0; q < TPW; ++q) {
         if (tmi[q] >= 0) {
-          const float* ha = Hs + 32 * tmi[q] + col;
-          const float* hb = Hs + 32 * tmj[q] + col;
+          if constexpr (PREC == PREC_BF16X3) {
+            // reduction step ks covers pixels 16 ks .. 16 ks + 15; lane half
+            // h holds pixels 16 ks + 8 h .. + 7 (dwords 8 ks + 4 h .. + 3)
+            const int ra = (32 * tmi[q] + col) * GT_STRIDE, rb = (32 * tmj[q] + col) * GT_STRIDE;
 #pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const int jr = 2 * u + half;
-            acc[q] = mfma_f32(ha[jr * KP] * ms[jr], hb[jr * KP], acc[q]);
+            for (int ks = 0; ks < 2; ++ks) {
+              const int d = 8 * ks + 4 * half;
+              const bf16x8 ah = *reinterpret_cast<const bf16x8*>(hmT_hi + ra + d);
+              const bf16x8 al = *reinterpret_cast<const bf16x8*>(hmT_lo + ra + d);
+              const bf16x8 bh = *reinterpret_cast<const bf16x8*>(hT_hi + rb + d);
+              const bf16x8 bl = *reinterpret_cast<const bf16x8*>(hT_lo + rb + d);
+              acc[q] = mfma_bf16x3(ah, al, bh, bl, acc[q]);
+            }
+          } else {
+            const float* ha = Hs + 32 * tmi[q] + col;
+            const float* hb = Hs + 32 * tmj[q] + col;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+              const int jr = 2 * u + half;
+              acc[q] = mfma_f32(ha[jr * KP] * ms[jr], hb[jr * KP], acc[q]);
+            }
           }
         }
       }
@@ -236,6 +292,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
     }
     __syncthreads();
 
+    bool warm_kept = false;  // the same in every thread
     if (a.warm) {
       // Warm start with fallback: the supplied coefficients are kept only if
       // their objective is not above that of the seeded cold start (the two
@@ -266,6 +323,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
         sc += wsel[1][w];
       }
       const bool keep = sw <= sc;  // false for a non-finite warm objective
+      warm_kept = keep;
       if (!keep && tid < K) csh[tid] = sm_uniform(key, (uint64_t)f * K + tid);
       if (a.fallback && tid == 0) a.fallback[f] = keep ? 0 : 1;
       __syncthreads();
@@ -273,71 +331,140 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
 
     // ---- iterations: (c G)_j with row j of G in registers (K <= 128) or
     // read from LDS (consecutive j across lanes, conflict-free) ------------
+    // Optional per-frame stop rule: every check_every iterations the model
+    // change since the previous check, d = c - c_prev, is tested against
+    // the model, d G d^T <= tol^2 c G c^T (both in FP64; c G is the
+    // denominator just formed, d G one more product).  A warm-started frame
+    // that has not met the rule by the cap restarts from the cold start.
     const int j = tid;
     const double bj = j < KP ? bsh[j] : 0.0;
     const f32x4* c4 = reinterpret_cast<const f32x4*>(csh);
-    if constexpr (KP <= 64) {
-      // One wave iterates: lane j keeps row j of G in registers and the
-      // coefficients travel through LDS.  A wave's LDS accesses execute in
-      // program order, so each iteration's broadcast reads see the previous
-      // iteration's writes without a workgroup barrier; the other waves wait
-      // at the end-of-frame barrier.
-      if (wave == 0) {
-        float g[KP];
+    float* dsh = csh + KP;
+    const f32x4* d4 = reinterpret_cast<const f32x4*>(dsh);
+    const int ce = a.check_every;
+    __shared__ int run_sh[2];  // iterations run, rule met
+    float g[KP <= 128 ? KP : 1];
+    if constexpr (KP <= 128) {
 #pragma unroll
-        for (int i = 0; i < KP; ++i) g[i] = (j < K && i < K) ? G[j * K + i] : 0.f;
-        float cj = j < KP ? csh[j] : 0.f;
-        for (int it = 0; it < a.iters; ++it) {
-          float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+      for (int i = 0; i < KP; ++i) g[i] = (j < K && i < K) ? G[j * K + i] : 0.f;
+    }
+    const float* gcol = G + (j < K ? j : 0);
+    // (v G)_j for a vector v in LDS
+    auto matvec = [&](const float* v, const f32x4* v4) -> float {
+      float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+      if constexpr (KP <= 128) {
 #pragma unroll
-          for (int i4 = 0; i4 < KQ; ++i4) {
-            const f32x4 cv = c4[i4];
-            d0 = fmaf(cv[0], g[4 * i4 + 0], d0);
-            d1 = fmaf(cv[1], g[4 * i4 + 1], d1);
-            d2 = fmaf(cv[2], g[4 * i4 + 2], d2);
-            d3 = fmaf(cv[3], g[4 * i4 + 3], d3);
+        for (int i4 = 0; i4 < KQ; ++i4) {
+          const f32x4 cv = v4[i4];
+          d0 = fmaf(cv[0], g[4 * i4 + 0], d0);
+          d1 = fmaf(cv[1], g[4 * i4 + 1], d1);
+          d2 = fmaf(cv[2], g[4 * i4 + 2], d2);
+          d3 = fmaf(cv[3], g[4 * i4 + 3], d3);
+        }
+      } else if (j < K) {
+        for (int i = 0; i < K; ++i) d0 = fmaf(v[i], gcol[i * K], d0);
+      }
+      return (d0 + d1) + (d2 + d3);
+    };
+    int its_total = 0;
+    bool met = false;
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1) {
+        // the warm start missed the rule by the cap: cold start, same cap
+        if (!(warm_kept && ce > 0 && !met)) break;
+        if (tid < KP) csh[tid] = tid < K ? sm_uniform(key, (uint64_t)f * K + tid) : 0.f;
+        if (a.fallback && tid == 0) a.fallback[f] = 2;
+        __syncthreads();
+      }
+      if constexpr (KP <= 64) {
+        // One wave iterates: lane j keeps row j of G in registers and the
+        // coefficients travel through LDS.  A wave's LDS accesses execute in
+        // program order, so each iteration's broadcast reads see the previous
+        // iteration's writes without a workgroup barrier; the other waves
+        // wait at the barrier below.
+        if (wave == 0) {
+          float cj = j < KP ? csh[j] : 0.f, cp = cj;
+          int it = 0;
+          bool stop = false;
+          for (; it < a.iters; ++it) {
+            const float den = matvec(csh, c4);
+            if (ce > 0 && it > 0 && it % ce == 0) {
+              const float dj = j < K ? cj - cp : 0.f;
+              if (j < KP) dsh[j] = dj;
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+              __builtin_amdgcn_wave_barrier();
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+              const float dg = matvec(dsh, d4);
+              const double q1 = wave_sum(j < K ? (double)dj * (double)dg : 0.0);
+              const double q2 = wave_sum(j < K ? (double)cj * (double)den : 0.0);
+              if (q1 <= a.tol2 * q2) {
+                stop = true;
+                break;
+              }
+              cp = cj;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (j < K) {
+              cj = mu_apply_d(cj, bj, (double)den, a.eps);
+              csh[j] = cj;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
           }
-          const float den = (d0 + d1) + (d2 + d3);
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
+          if (lane == 0) {
+            run_sh[0] = it;
+            run_sh[1] = stop ? 1 : 0;
+          }
+        }
+      } else {
+        float cj = j < K ? csh[j] : 0.f, cp = cj;
+        int it = 0;
+        bool stop = false;
+        for (; it < a.iters; ++it) {
+          const float den = matvec(csh, c4);
+          if (ce > 0 && it > 0 && it % ce == 0) {
+            const float dj = j < K ? cj - cp : 0.f;
+            if (j < KP) dsh[j] = dj;
+            __syncthreads();
+            const float dg = matvec(dsh, d4);
+            const double q1 = wave_sum(j < K ? (double)dj * (double)dg : 0.0);
+            const double q2 = wave_sum(j < K ? (double)cj * (double)den : 0.0);
+            if (lane == 0) {
+              wsel[0][wave] = q1;
+              wsel[1][wave] = q2;
+            }
+            __syncthreads();
+            double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int w = 0; w < NWV; ++w) {
+              s1 += wsel[0][w];
+              s2 += wsel[1][w];
+            }
+            if (s1 <= a.tol2 * s2) {  // the same value in every thread
+              stop = true;
+              break;
+            }
+            cp = cj;
+          }
+          __syncthreads();
           if (j < K) {
             cj = mu_apply_d(cj, bj, (double)den, a.eps);
             csh[j] = cj;
           }
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
+          __syncthreads();
+        }
+        if (tid == 0) {
+          run_sh[0] = it;
+          run_sh[1] = stop ? 1 : 0;
         }
       }
-    } else if constexpr (KP <= 128) {
-      float g[KP];
-#pragma unroll
-      for (int i = 0; i < KP; ++i) g[i] = (j < K && i < K) ? G[j * K + i] : 0.f;
-      for (int it = 0; it < a.iters; ++it) {
-        float den = 0.f;
-#pragma unroll
-        for (int i4 = 0; i4 < KQ; ++i4) {
-          const f32x4 cv = c4[i4];
-          den = fmaf(cv[0], g[4 * i4 + 0], den);
-          den = fmaf(cv[1], g[4 * i4 + 1], den);
-          den = fmaf(cv[2], g[4 * i4 + 2], den);
-          den = fmaf(cv[3], g[4 * i4 + 3], den);
-        }
-        __syncthreads();
-        if (j < K) csh[j] = mu_apply_d(csh[j], bj, (double)den, a.eps);
-        __syncthreads();
-      }
-    } else {
-      const float* gcol = G + (j < K ? j : 0);
-      for (int it = 0; it < a.iters; ++it) {
-        float den = 0.f;
-        if (j < K) {
-          for (int i = 0; i < K; ++i) den = fmaf(csh[i], gcol[i * K], den);
-        }
-        __syncthreads();
-        if (j < K) csh[j] = mu_apply_d(csh[j], bj, (double)den, a.eps);
-        __syncthreads();
-      }
+      __syncthreads();
+      its_total += run_sh[0];
+      met = run_sh[1] != 0;
+      __syncthreads();
     }
+    if (a.iters_out && tid == 0) a.iters_out[f] = its_total;
     if (j < K) a.C_out[(int64_t)f * K + j] = csh[j];
     if (a.ticks && tid == 0) {
       a.ticks[2 * (int64_t)f] = tick0;
@@ -348,15 +475,16 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   if (bad) atomicOr(a.status, bad);
 }
 
-size_t gram_lds_bytes(int K, int KP) {
-  const int goff = (std::max(K * K, 32 * KP + 64) + 3) & ~3;
-  return (size_t)goff * 4 + (size_t)KP * 8 + (size_t)KP * 4;
+size_t gram_lds_bytes(int K, int KP, int prec) {
+  const int stage = 32 * KP + 64 + (prec == PREC_BF16X3 ? 4 * KP * GT_STRIDE : 0);
+  const int goff = (std::max(K * K, stage) + 3) & ~3;
+  return (size_t)goff * 4 + (size_t)KP * 8 + (size_t)KP * 4 * 2;  // G | b | c, d
 }
 
-template <int KP, bool RAGGED>
+template <int KP, bool RAGGED, int PREC>
 static hipError_t gram_launch(const GramArgs& a, int max_blocks, hipStream_t s, int* grid_out) {
-  const size_t lds = gram_lds_bytes(a.K, KP);
-  auto fn = k_gram<KP, RAGGED>;
+  const size_t lds = gram_lds_bytes(a.K, KP, PREC);
+  auto fn = k_gram<KP, RAGGED, PREC>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -374,24 +502,27 @@ static hipError_t gram_launch(const GramArgs& a, int max_blocks, hipStream_t s, 
   return hipGetLastError();
 }
 
-template <bool RAGGED>
+template <bool RAGGED, int PREC>
 static hipError_t gram_kp(int kp, const GramArgs& a, int max_blocks, hipStream_t s, int* g) {
   switch (kp) {
-    case 32: return gram_launch<32, RAGGED>(a, max_blocks, s, g);
-    case 64: return gram_launch<64, RAGGED>(a, max_blocks, s, g);
-    case 96: return gram_launch<96, RAGGED>(a, max_blocks, s, g);
-    case 128: return gram_launch<128, RAGGED>(a, max_blocks, s, g);
-    case 160: return gram_launch<160, RAGGED>(a, max_blocks, s, g);
-    case 192: return gram_launch<192, RAGGED>(a, max_blocks, s, g);
-    case 224: return gram_launch<224, RAGGED>(a, max_blocks, s, g);
+    case 32: return gram_launch<32, RAGGED, PREC>(a, max_blocks, s, g);
+    case 64: return gram_launch<64, RAGGED, PREC>(a, max_blocks, s, g);
+    case 96: return gram_launch<96, RAGGED, PREC>(a, max_blocks, s, g);
+    case 128: return gram_launch<128, RAGGED, PREC>(a, max_blocks, s, g);
+    case 160: return gram_launch<160, RAGGED, PREC>(a, max_blocks, s, g);
+    case 192: return gram_launch<192, RAGGED, PREC>(a, max_blocks, s, g);
+    case 224: return gram_launch<224, RAGGED, PREC>(a, max_blocks, s, g);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, hipStream_t s,
                        int* grid_out) {
-  return ragged ? gram_kp<true>(kp, a, max_blocks, s, grid_out)
-                : gram_kp<false>(kp, a, max_blocks, s, grid_out);
+  if (a.prec == PREC_BF16X3)
+    return ragged ? gram_kp<true, PREC_BF16X3>(kp, a, max_blocks, s, grid_out)
+                  : gram_kp<false, PREC_BF16X3>(kp, a, max_blocks, s, grid_out);
+  return ragged ? gram_kp<true, PREC_FP32>(kp, a, max_blocks, s, grid_out)
+                : gram_kp<false, PREC_FP32>(kp, a, max_blocks, s, grid_out);
 }
 
 // ---------------------------------------------------------------------------

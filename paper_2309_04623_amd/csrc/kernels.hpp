@@ -211,8 +211,15 @@ struct GramArgs {
   int warm;            // C_init is a warm start: fall back to the cold start
                        // per frame when its objective is lower
   int* fallback;       // nullable: per frame, 1 where the cold start was used
+  int prec;            // products of G: PREC_FP32 or PREC_BF16X3
+  // per-frame stop rule (check_every > 0): stop when the model change since
+  // the previous check satisfies d G d^T <= tol2 * c G c^T; a warm start
+  // that misses it by the cap restarts cold (fallback = 2)
+  int check_every;
+  double tol2;
+  int* iters_out;      // nullable: iterations run per frame
 };
-size_t gram_lds_bytes(int K, int KP);
+size_t gram_lds_bytes(int K, int KP, int prec);
 hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, hipStream_t s,
                        int* grid_out);
 // Longest-first processing order of CSR frames (equal sizes by index): a

@@ -74,6 +74,7 @@ _SIGS = {
                                           ctypes.POINTER(Report), _vp]),
     "nmf_device_clock_khz": (ctypes.c_double, [_vp]),
     "nmf_warm_fallbacks": (ctypes.c_int64, [_vp]),
+    "nmf_frame_iters": (ctypes.c_int64, [_vp, _vp, _i64]),
     "nmf_subtract": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp]),
     "nmf_warmstart_param_count": (ctypes.c_int64, [_i32]),
     "nmf_warmstart_init": (ctypes.c_int, [_vp, _vp, _i32, _u64, _vp]),
@@ -261,10 +262,13 @@ def build_basis(V, M, k, iters, *, precision="fp32", W_init=None, H_init=None, s
 
 
 def project(H, T, MT, iters, *, C_init=None, precision="fp32", seed=0, flags=0, eps=1e-30,
-            split=0, want_objective=False, gram=False, warm=False, handle=None):
+            split=0, want_objective=False, gram=False, warm=False, tol=0.0, check_every=0,
+            handle=None):
     """Target modelling: per-frame coefficients with the basis fixed
     (``gram=True``: through per-frame masked Gram matrices; ``warm=True``:
-    C_init is a warm start with per-frame fallback to the cold start)."""
+    C_init is a warm start with per-frame fallback to the cold start;
+    ``tol``/``check_every``: per-frame stop rule of the Gram form, see
+    frame_iters())."""
     if gram:
         flags |= F_MASKED_GRAM
     if warm:
@@ -277,7 +281,7 @@ def project(H, T, MT, iters, *, C_init=None, precision="fp32", seed=0, flags=0, 
     f32 = torch.float32
     C = torch.empty((f, k), dtype=f32, device=H.device)
     obj = torch.empty(f, dtype=torch.float64, device=H.device) if want_objective else None
-    prm = make_params(k, iters, precision, seed, flags, eps, split)
+    prm = make_params(k, iters, precision, seed, flags, eps, split, tol, check_every)
     rep = _new_report()
     _check(lib().nmf_project(h.h, _dev_ptr(H, "H", f32), k, p, _dev_ptr(T, "T", f32),
                              _dev_ptr(MT, "M_T", f32), f, ctypes.byref(prm),
@@ -397,7 +401,8 @@ def profile_get(handle: Handle, kernel_class: int):
 
 
 def project_ragged(H, offsets, pix, val, wt, iters, *, C_init=None, seed=0, flags=0, eps=1e-30,
-                   want_ticks=False, warm=False, handle=None):
+                   want_ticks=False, warm=False, precision="fp32", tol=0.0, check_every=0,
+                   handle=None):
     """Projection of CSR frames (one persistent launch, masked Gram form).
     offsets: int64 (f+1), pix: int32, val/wt: float32 (wt may be None)."""
     if warm:
@@ -410,7 +415,7 @@ def project_ragged(H, offsets, pix, val, wt, iters, *, C_init=None, seed=0, flag
     nnz = pix.shape[0]
     C = torch.empty((f, k), dtype=torch.float32, device=H.device)
     ticks = torch.zeros(2 * f, dtype=torch.int64, device=H.device) if want_ticks else None
-    prm = make_params(k, iters, "fp32", seed, flags, eps)
+    prm = make_params(k, iters, precision, seed, flags, eps, 0, tol, check_every)
     rep = _new_report()
     _check(lib().nmf_project_ragged(
         h.h, _dev_ptr(H, "H", torch.float32), k, p, f, _dev_ptr(offsets, "offsets", torch.int64),
@@ -425,6 +430,19 @@ def warm_fallbacks(handle=None, device=0) -> int:
     start (-1 if none ran on the handle)."""
     h = handle or default_handle(device)
     return int(lib().nmf_warm_fallbacks(h.h))
+
+
+def frame_iters(handle=None, device=0):
+    """Iterations per frame of the last masked-Gram projection with a stop
+    rule on the handle (int32 numpy array; None if it had none)."""
+    import numpy as np
+    h = handle or default_handle(device)
+    n = _check(int(lib().nmf_frame_iters(h.h, None, 0)))
+    if n == 0:
+        return None
+    buf = np.zeros(n, np.int32)
+    _check(int(lib().nmf_frame_iters(h.h, buf.ctypes.data, n)))
+    return buf
 
 
 def device_clock_khz(handle=None, device=0) -> float:

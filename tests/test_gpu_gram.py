@@ -24,10 +24,17 @@ def _photon_frames(H, f, seed, peak=1e4, mask_frac=0.1):
     return T.astype(np.float32), MT.astype(np.float32)
 
 
-def _compare(T, MT, H, Cg, Co, tol_j=1e-5, tol_m=1e-4, derived=False):
+# Relative model error of one product: 16 FP32 ulps for FP32, and for the
+# bf16 x 3 split form the terms it drops (lo*lo and the two residuals of the
+# split, each up to 2^-18 of the product), 3 * 2^-18 ~ 1.1e-5.
+MODEL_ULP = {"fp32": 1e-6, "bf16x3": 1.1e-5}
+
+
+def _compare(T, MT, H, Cg, Co, tol_j=1e-5, tol_m=1e-4, derived=False, precision="fp32"):
     """Objective and model bars.  With ``derived`` the objective bar is
-    max(tol_j, 2e-6 * snr): a 1e-6 relative change of the FP32 model moves J
-    by about 2e-6 times the model-to-residual ratio snr."""
+    max(tol_j, 2 d snr): a relative change d of the model (MODEL_ULP of the
+    precision form) moves J by about 2 d times the model-to-residual ratio
+    snr."""
     Jo = nmf64.frame_objective(T, MT, H, Co)
     Jg = nmf64.frame_objective(T, MT, H, Cg)
     # frames the basis fits exactly (fewer pixels than components) have J ~ 0:
@@ -39,7 +46,7 @@ def _compare(T, MT, H, Cg, Co, tol_j=1e-5, tol_m=1e-4, derived=False):
     Th = np.where(MT > 0, T, 0.0)
     mod = Co @ H
     snr = np.linalg.norm(MT * mod, axis=1) / np.maximum(np.linalg.norm(MT * (Th - mod), axis=1), 1e-300)
-    bar = np.maximum(tol_j, 2e-6 * snr) if derived else tol_j
+    bar = np.maximum(tol_j, 2 * MODEL_ULP[precision] * snr) if derived else tol_j
     print(f"  relJ={relJ.max():.3e} model={model:.3e} snr={snr.max():.1f}", flush=True)
     assert np.all(relJ <= bar) and model <= tol_m
     assert np.all(Cg >= 0)
@@ -100,7 +107,8 @@ def test_ragged_parity(k, p, sizes, binary):
     Co = nmf64.project_ragged(offs, pix, val, wt, H, C0, iters)
     T, MT = nmf64.ragged_to_dense(offs, pix, val, wt, p)
     nonempty = [i for i in range(f) if sizes[i] > 0]
-    _compare(T[nonempty], MT[nonempty], H, Cg[nonempty], Co[nonempty])
+    _compare(T[nonempty], MT[nonempty], H, Cg[nonempty], Co[nonempty], derived=True,
+             precision="bf16x3")
     for i in range(f):
         if sizes[i] == 0:  # no data: den = 0 keeps the start values
             assert np.array_equal(Cg[i], C0[i].astype(np.float32))
@@ -167,27 +175,67 @@ def test_gram_projection_reaches_nnls():
         assert nnls.cost(G, b, c, C[i]) - j <= 1e-5 * j
 
 
-def test_cfg4_shaped_batch_sample():
-    """MIRI-shaped CSR batch (224 x 288 px frames keeping 1000-64512 pixels
-    nearest the star outside the cross, K = 200, 300 iterations): sampled
-    frames match the oracle."""
-    k, ny, nx = 200, 224, 288
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", ["bf16x3", "fp32"])
+def test_cfg4_batch_256_sampled_frames(precision):
+    """The batched workload at full size: 4096 MIRI-shaped CSR frames
+    (224 x 288 px, keeping P_f ~ U{10000..64512} pixels nearest the star
+    outside the cross), K = 200, 300 iterations, one persistent launch.
+    256 frames drawn at random (seeded) match the oracle (Gram form, equal
+    to the direct form in exact arithmetic) frame by frame."""
+    k, ny, nx, iters = 200, 224, 288, 300
     g = np.random.default_rng(0)
     H = synth.components_speckle(g, k, ny, nx).astype(np.float32)
-    rf = synth.make_ragged(H.astype(np.float64), ny, nx, 24, 1000, 64512)
-    say("cfg4-shaped 24 frames")
-    C, _ = nmf.project_ragged(dev(H), dev_i64(rf.offsets), dev_i32(rf.pix), dev(rf.val), None, 300,
-                              seed=2)
+    rf = synth.make_ragged(H.astype(np.float64), ny, nx, 4096, 10000, 64512)
+    say("cfg4 4096 frames", precision)
+    C, ticks, _ = nmf.project_ragged(dev(H), dev_i64(rf.offsets), dev_i32(rf.pix), dev(rf.val),
+                                     None, iters, seed=2, precision=precision, want_ticks=True)
     Cg = host(C)
-    C0 = prng.init_matrix(2, prng.MAT_C, 24, k)
-    sel = [0, 11, 23]
+    C0 = prng.init_matrix(2, prng.MAT_C, rf.f, k)
+    sel = np.sort(np.random.default_rng(1).choice(rf.f, 256, replace=False))
     o = rf.offsets
+    worst_j = worst_m = 0.0
     for i in sel:
         sub_off = np.array([0, o[i + 1] - o[i]])
         sl = slice(o[i], o[i + 1])
-        co = nmf64.project_ragged(sub_off, rf.pix[sl], rf.val[sl], rf.wt[sl], H, C0[i:i + 1], 300)
         T, MT = nmf64.ragged_to_dense(sub_off, rf.pix[sl], rf.val[sl], rf.wt[sl], ny * nx)
-        _compare(T, MT, H, Cg[i:i + 1], co, derived=True)
+        co = nmf64.project_gram(T, MT, H, C0[i:i + 1], iters)
+        Jo = nmf64.frame_objective(T, MT, H, co)[0]
+        Jg = nmf64.frame_objective(T, MT, H, Cg[i:i + 1])[0]
+        Th = np.where(MT > 0, T, 0.0)
+        mod = co @ H
+        snr = np.linalg.norm(MT * mod) / np.linalg.norm(MT * (Th - mod))
+        relj = abs(Jg - Jo) / Jo
+        model = rel_model_err(MT, Cg[i:i + 1] @ H, mod)
+        worst_j, worst_m = max(worst_j, relj), max(worst_m, model)
+        bar = max(1e-5, 2 * MODEL_ULP[precision] * snr)
+        assert relj <= bar and model <= 1e-4, (i, relj, model, snr)
+    print(f"  256 sampled frames: max relJ={worst_j:.3e} max model={worst_m:.3e}", flush=True)
+    t = host(ticks).astype(np.int64).reshape(rf.f, 2)
+    assert np.all(t[:, 0] > 0) and np.all(t[:, 1] >= t[:, 0])
+
+
+@pytest.mark.parametrize("k,p,sizes", [(30, 6400, [6400, 0, 3000, 31, 32, 33, 5000]),
+                                       (100, 3000, [2999, 1500, 64, 700]),
+                                       (200, 2500, [2500, 1200, 300])])
+def test_ragged_bf16x3_parity(k, p, sizes):
+    """Split-precision Gram products on CSR frames: model within 1e-4, the
+    objective within the bar derived from the split form's product error
+    (frames of about K pixels are fitted almost exactly, so their objective
+    is a small difference that a model change moves a lot)."""
+    H = _basis(k, p, seed=k + 1)
+    offs, pix, val, wt = _ragged(H, sizes, seed=k, binary=True)
+    f = len(sizes)
+    C0 = prng.init_matrix(9, prng.MAT_C, f, k)
+    say("ragged bf16x3", k, p, sizes)
+    C, _ = nmf.project_ragged(dev(H), dev_i64(offs), dev_i32(pix), dev(val), None, 100, seed=9,
+                              precision="bf16x3")
+    Cg = host(C)
+    Co = nmf64.project_ragged(offs, pix, val, wt, H, C0, 100)
+    T, MT = nmf64.ragged_to_dense(offs, pix, val, wt, p)
+    nonempty = [i for i in range(f) if sizes[i] > 0]
+    _compare(T[nonempty], MT[nonempty], H, Cg[nonempty], Co[nonempty], derived=True,
+             precision="bf16x3")
 
 
 def test_ragged_many_frames_longest_first_order_is_a_permutation():
@@ -212,3 +260,78 @@ def test_ragged_many_frames_longest_first_order_is_a_permutation():
     assert np.max(np.abs(Cg - Co) / scale) < 1e-4
     t = host(ticks).astype(np.int64).reshape(f, 2)
     assert np.all(t[:, 0] > 0) and np.all(t[:, 1] >= t[:, 0])
+
+
+def _check_ratio(T, MT, H, C0, t, ce):
+    """sqrt(d G d^T / c G c^T) of the oracle's iterate at check t (d: change
+    since the check at t - ce)."""
+    c = nmf64.project_gram(T, MT, H, C0, t)[0]
+    cp = nmf64.project_gram(T, MT, H, C0, t - ce)[0]
+    G = (H.astype(np.float64) * np.where(MT[0] > 0, MT[0], 0.0)[None, :]) @ H.T.astype(np.float64)
+    d = c - cp
+    return np.sqrt(max(d @ G @ d, 0.0) / (c @ G @ c))
+
+
+@pytest.mark.parametrize("k,ce,tol,precision", [(20, 10, 1e-4, "fp32"), (150, 25, 3e-4, "fp32"),
+                                                (60, 10, 1e-4, "bf16x3")])
+def test_stop_rule_matches_oracle(k, ce, tol, precision):
+    """Per-frame stop rule: each frame stops at the oracle's count or one
+    check period away (the FP32 iterate and its model change differ from
+    the FP64 ones in the last digits, which can move a test that sits at the
+    threshold), the stop is legitimate for the oracle's iterate (its ratio
+    at that check within 20% of tol, the previous check's not below tol/1.2),
+    and the coefficients match the oracle's fixed-count iterate at the
+    frame's own count."""
+    f, p, cap = 24, 2000, 3000
+    H = _basis(k, p, seed=k + 1)
+    T, MT = _photon_frames(H, f, seed=k + 2)
+    C0 = prng.init_matrix(7, prng.MAT_C, f, k)
+    say("stop rule", k, ce, tol, precision)
+    C, rep = nmf.project(dev(H), dev(T), dev(MT), cap, seed=7, gram=True, precision=precision,
+                         tol=tol, check_every=ce)
+    its = nmf.frame_iters()
+    assert its is not None and len(its) == f
+    Cg = host(C)
+    _, its_o, _ = nmf64.project_gram_tol(T, MT, H, C0, cap, ce, tol)
+    print(f"  iterations gpu {its.min()}..{its.max()}, oracle {its_o.min()}..{its_o.max()}, "
+          f"equal {np.sum(its == its_o)}/{f}", flush=True)
+    assert rep["iters_run"] == its.max()
+    assert np.all(its % ce == 0) and np.all(its < cap)
+    assert np.all(np.abs(its - its_o) <= ce) and np.sum(its == its_o) >= 0.75 * f
+    for i in range(f):
+        sl = slice(i, i + 1)
+        assert _check_ratio(T[sl], MT[sl], H, C0[sl], int(its[i]), ce) <= 1.2 * tol
+        if its[i] > ce:
+            assert _check_ratio(T[sl], MT[sl], H, C0[sl], int(its[i]) - ce, ce) >= tol / 1.2
+        Co = nmf64.project_gram(T[sl], MT[sl], H, C0[sl], int(its[i]))
+        _compare(T[sl], MT[sl], H, Cg[sl], Co, derived=True, precision=precision)
+
+
+def test_stop_rule_warm_start_restart_and_fallback():
+    """Warm starts under the stop rule: a start worse than the cold one is
+    replaced from the start; a kept start that misses the rule by the cap
+    restarts cold with the same cap (iterations add up, flagged as fallen
+    back, the call warns that the rule was not met); a kept start at the
+    solution stops at the first check.  Against the oracle's warm rule."""
+    k, p, f, cap, ce = 12, 1500, 12, 30, 5
+    H = _basis(k, p, seed=21)
+    T, MT = _photon_frames(H, f, seed=22)
+    Cc = prng.init_matrix(3, prng.MAT_C, f, k)
+    Cw = np.empty((f, k), np.float32)
+    Cw[:4] = 1e3                                            # rejected
+    Cw[4:8] = nmf64.project_gram(T[4:8], MT[4:8], H, Cc[4:8], 20)   # kept, misses tol by cap
+    Cw[8:] = nmf64.project_gram(T[8:], MT[8:], H, Cc[8:], 30000)     # kept, at the solution
+    say("stop rule warm")
+    tol = 1e-6
+    C, rep = nmf.project(dev(H), dev(T), dev(MT), cap, seed=3, gram=True, C_init=dev(Cw),
+                         warm=True, tol=tol, check_every=ce)
+    its = nmf.frame_iters()
+    Co, its_o, fb_o = nmf64.project_gram_tol(T, MT, H, Cw, cap, ce, tol, C_cold=Cc)
+    print(f"  gpu its {its.tolist()}\n  oracle its {its_o.tolist()} fallback {fb_o.tolist()}",
+          flush=True)
+    assert list(fb_o[:8]) == [1] * 4 + [2] * 4
+    assert np.array_equal(its[:8], its_o[:8])
+    assert nmf.warm_fallbacks() == int(np.sum(fb_o != 0))
+    assert rep["status_flags"] & (1 << nmf.NMF_WARN_MAXITER)  # frames 0..7 never met it
+    assert np.all(its[8:] <= 2 * ce)
+    _compare(T[:8], MT[:8], H, host(C)[:8], Co[:8])

@@ -430,3 +430,59 @@ def test_build_basis_tol_stops_at_the_rule():
     assert run == first + 1
     Wr, Hr, Jr = nmf64.build_basis(V, M, W, H, run)
     assert np.array_equal(Wt, Wr) and np.array_equal(Jt, Jr)
+
+
+def test_projection_stop_rule_by_hand_and_limits():
+    """Per-frame stop rule of the projection: hand-checked decision on a K = 1
+    frame (one step lands on the optimum, so the change at the next check
+    is 0), no stop with tol = 0 unless the start is a fixed point, and the
+    stopped iterate matches the fixed-count run at the same count."""
+    H = np.array([[1.0, 2.0, 3.0]])
+    T = np.array([[2.0, 4.0, 6.0]])       # t = 2 h exactly: w* = 2
+    MT = np.ones_like(T)
+    C, its, _ = nmf64.project_gram_tol(T, MT, H, np.array([[0.5]]), 50, 2, 1e-12)
+    # iteration 1: w = 0.5 * (b / (w G)) = 0.5 * 28 / 7 = 2; iteration 2
+    # keeps 2; the check at t = 2 sees w_2 - w_0 = 1.5 (no stop), the one at
+    # t = 4 sees 0 (stop)
+    assert its[0] == 4 and C[0, 0] == 2.0
+    g = np.random.default_rng(3)
+    Hr = g.gamma(1, 1, (4, 60))
+    Tr = g.gamma(2, 1, (3, 4)) @ Hr + np.abs(g.normal(0, 0.1, (3, 60)))
+    Mr = (g.random(Tr.shape) > 0.1).astype(float)
+    C0 = g.uniform(0.1, 1, (3, 4))
+    C1, its1, _ = nmf64.project_gram_tol(Tr, Mr, Hr, C0, 200, 10, 0.0)
+    assert np.all(its1 == 200)
+    assert np.allclose(C1, nmf64.project_gram(Tr, Mr, Hr, C0, 200), rtol=1e-12, atol=0)
+    C2, its2, _ = nmf64.project_gram_tol(Tr, Mr, Hr, C0, 5000, 10, 1e-3)
+    assert np.all(its2 % 10 == 0) and np.all(its2 < 5000)
+    for f in range(3):
+        ref = nmf64.project_gram(Tr[f:f + 1], Mr[f:f + 1], Hr, C0[f:f + 1], int(its2[f]))
+        assert np.allclose(C2[f], ref[0], rtol=1e-12, atol=0)
+
+
+def test_projection_stop_rule_warm_restart():
+    """Warm start under the stop rule: the exact optimum as warm start stops
+    at the first check with the start kept; a warm start worse than the cold
+    one is replaced by it from the start (the run equals the cold run); a
+    kept warm start that misses the rule by the cap is followed by a full
+    cold run (iterations add up, the result is the cold run's)."""
+    H = np.array([[1.0, 2.0, 3.0]])
+    T = np.array([[2.0, 4.0, 6.0]])
+    MT = np.ones_like(T)
+    cold = np.array([[0.5]])
+    C, its, fb = nmf64.project_gram_tol(T, MT, H, np.array([[2.0]]), 50, 3, 1e-12, C_cold=cold)
+    assert its[0] == 3 and fb[0] == 0 and C[0, 0] == 2.0
+    g = np.random.default_rng(5)
+    Hr = g.gamma(1, 1, (5, 80))
+    Tr = g.gamma(2, 1, (4, 5)) @ Hr + np.abs(g.normal(0, 0.1, (4, 80)))
+    Mr = (g.random(Tr.shape) > 0.1).astype(float)
+    Cc = g.uniform(0.1, 1, (4, 5))
+    bad = 1e3 * np.ones((4, 5))
+    C, its, fb = nmf64.project_gram_tol(Tr, Mr, Hr, bad, 40, 5, 1e-3, C_cold=Cc)
+    Cr, itsr, _ = nmf64.project_gram_tol(Tr, Mr, Hr, Cc, 40, 5, 1e-3)
+    assert np.all(fb == 1) and np.array_equal(its, itsr) and np.array_equal(C, Cr)
+    # near the solution but the rule is unreachable within the cap
+    near = nmf64.project_gram(Tr, Mr, Hr, Cc, 30)
+    C, its, fb = nmf64.project_gram_tol(Tr, Mr, Hr, near, 20, 5, 1e-14, C_cold=Cc)
+    assert np.all(fb == 2) and np.all(its == 40)
+    assert np.allclose(C, nmf64.project_gram(Tr, Mr, Hr, Cc, 20), rtol=1e-12, atol=0)
