@@ -164,7 +164,13 @@ int nmf_objective(nmf_handle h, const float* V, const float* M, const float* W,
 /* ---- basis construction --------------------------------------------------
  * Iterates Eq. 3 (H-rule, then the W-rule with the new H) prm->max_iter
  * times from (W_init, H_init), or from the seeded U(0,1) init when those are
- * NULL.  After each update x := max(x, floor_eps); a zero denominator keeps
+ * NULL.  NMF_F_WARM_START (W_init and H_init required: a warm start of the
+ * component initialisation, e.g. a prior basis and the coefficients
+ * nmf_warmstart_infer predicts on it for each library image): the supplied
+ * start is kept only if its Eq. 2 cost is not above the seeded cold start's
+ * (one synchronisation before the first iteration); otherwise the build
+ * starts cold, rep->status_flags gets NMF_RS_WARM_FALLBACK and
+ * nmf_warm_fallbacks() returns 1.  After each update x := max(x, floor_eps); a zero denominator keeps
  * the factor.  Data under zero weight are ignored whatever their value.
  * Stop rule (Sec. 2: iterate until the change reaches a set value or the
  * cap), on when tol > 0 and check_every = c > 0: J[t] is the Eq. 2 cost of
@@ -239,7 +245,8 @@ int nmf_project_ragged(nmf_handle h, const float* H, int64_t k, int64_t p, int64
 #define NMF_RS_WARM_FALLBACK (1 << 8)
 
 /* Frames of the last synchronous warm-started projection on h that fell back
- * to the cold start (-1 if none ran). */
+ * to the cold start, or 1/0 after a warm-started basis build (-1 if none
+ * ran). */
 int64_t nmf_warm_fallbacks(nmf_handle h);
 
 /* Iterations each frame ran in the last synchronous masked-Gram projection

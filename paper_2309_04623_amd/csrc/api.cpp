@@ -964,6 +964,36 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   B.Mb = BbT;
   B.tiles_per_split = cb.tiles_per_split;
   B.partial = partial;
+  // Warm start of the component initialisation (NMF_F_WARM_START with W_init
+  // and H_init, e.g. a prior basis and the coefficients a network predicts
+  // on it): the supplied start is kept only if its Eq. 2 cost is not above
+  // that of the seeded cold start.  Decided once, before the first
+  // iteration, with one synchronisation.
+  bool fell_back = false;
+  if (prm->flags & NMF_F_WARM_START) {
+    if (!W_init || !H_init) return fail(NMF_ERR_ARG, "NMF_F_WARM_START needs W_init and H_init");
+    double* Jwc;
+    if ((rc = ws(h, "Jwarmcold", 2, &Jwc))) return rc;
+    const int nO = pass_blocks(KP, ca, ptile);
+    // cold start first, then the warm one, which normally stays in place
+    for (int w = 0; w < 2; ++w) {
+      const FactorFillArgs fw = fill_args(Wf, w ? W_init : nullptr, 0, prm->seed, 0, K);
+      const FactorFillArgs fh = fill_args(Hf, w ? H_init : nullptr, 1, prm->seed, 1, K);
+      LAUNCH(NMF_K_OTHER, launch_factor_fill(fw, s));
+      LAUNCH(NMF_K_OTHER, launch_factor_fill(fh, s));
+      LAUNCH(NMF_K_OBJECTIVE, launch_pass(prec, KP, MODE_OBJ, ca, A, ptile, s));
+      LAUNCH(NMF_K_OTHER, launch_reduce_f64(part, nO, Jwc + (1 - w), nullptr, s));
+    }
+    double hj[2] = {0.0, 0.0};  // warm, cold
+    HIP_TRY(hipMemcpyAsync(hj, Jwc, sizeof(hj), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    fell_back = !(hj[0] <= hj[1]);  // also for a non-finite warm cost
+    if (fell_back) {
+      LAUNCH(NMF_K_OTHER, launch_factor_fill(fill_args(Wf, nullptr, 0, prm->seed, 0, K), s));
+      LAUNCH(NMF_K_OTHER, launch_factor_fill(fill_args(Hf, nullptr, 1, prm->seed, 1, K), s));
+    }
+    h->last_fallbacks = fell_back ? 1 : 0;
+  }
   if ((prm->flags & NMF_F_AUTOTUNE) && KP < KP_WIDE) {
     const std::string ka = key_of("tuneA", {(uint64_t)n, (uint64_t)p, (uint64_t)KP, (uint64_t)prec});
     const std::string kb = key_of("tuneB", {(uint64_t)n, (uint64_t)p, (uint64_t)KP, (uint64_t)prec});
@@ -1111,7 +1141,7 @@ int nmf_build_basis(nmf_handle h, const float* V, const float* M, int64_t n, int
   else if (warn & (1 << NMF_WARN_MAXITER)) result = NMF_WARN_MAXITER;
   if (rep) {
     rep->iters_run = iters_run;
-    rep->status_flags = warn;
+    rep->status_flags = warn | (fell_back ? NMF_RS_WARM_FALLBACK : 0);
     rep->objective = hostJ[iters_run];
     rep->objective_rel = mv2 > 0 ? hostJ[iters_run] / mv2 : 0.0;
     rep->elapsed_ms = ms;
@@ -1724,39 +1754,74 @@ int nmf_warmstart_train(nmf_handle h, float* state, const float* X, const float*
   const WsLayout L(k);
   const int x3 = x3_of(precision);
   const int b = (int)std::min<int64_t>(batch, m);
+  const int nb = (int)(m / b);  // full minibatches per epoch
   WsBufs B;
   int rc;
-  if ((rc = ws_bufs(h, b, k, L.count, &B))) return rc;
+  int *perm_d, *ctr;
+  float* coef;
+  double* eacc;
+  if ((rc = ws_bufs(h, b, k, L.count, &B)) || (rc = ws(h, "ws.perm", (size_t)m, &perm_d)) ||
+      (rc = ws(h, "ws.ctr", 2, &ctr)) || (rc = ws(h, "ws.coef", 2, &coef)) ||
+      (rc = ws(h, "ws.eacc", 1, &eacc)))
+    return rc;
+  constexpr float B1 = 0.9f, B2 = 0.999f, AEPS = 1e-8f;
+  // An epoch is one captured graph: per minibatch the rows perm[cursor ..
+  // cursor + b) are gathered, the forward and backward passes and the Adam
+  // step run, the batch loss is added to the epoch sum, and the cursor and
+  // step advance on the device.  The step count t runs on across epochs.
+  LAUNCH(NMF_K_OTHER, launch_train_ctr(ctr, coef, 0, b, B1, B2, s));
+  auto epoch = [&](hipStream_t st) -> hipError_t {
+    hipError_t e;
+    if ((e = launch_set_int(ctr, 0, st))) return e;  // cursor only; t continues
+    for (int i = 0; i < nb; ++i) {
+      if ((e = timed(h, NMF_K_OTHER, st, [&]() {
+             return launch_gather_cur(X, perm_d, ctr, b, WS_IN, B.Xb, st);
+           })))
+        return e;
+      if ((e = timed(h, NMF_K_OTHER, st,
+                     [&]() { return launch_gather_cur(s_in, perm_d, ctr, b, 1, B.sb, st); })))
+        return e;
+      if ((e = timed(h, NMF_K_OTHER, st,
+                     [&]() { return launch_gather_cur(c_star, perm_d, ctr, b, k, B.cb, st); })))
+        return e;
+      if ((e = ws_forward(h, state, L, B.Xb, B.sb, b, k, x3, B, B.W, st))) return e;
+      if ((e = ws_backward(h, state, L, B.Xb, B.sb, B.cb, G, b, k, x3, B, st))) return e;
+      if ((e = timed(h, NMF_K_OTHER, st, [&]() {
+             return launch_adam_dev(state, B.grads, state + L.count, state + 2 * L.count, L.count,
+                                    lr, B1, B2, AEPS, coef, st);
+           })))
+        return e;
+      if ((e = timed(h, NMF_K_OTHER, st,
+                     [&]() { return launch_loss_accum(B.lrow, b, eacc, i == 0, st); })))
+        return e;
+      if ((e = timed(h, NMF_K_OTHER, st,
+                     [&]() { return launch_train_ctr(ctr, coef, 1, b, B1, B2, st); })))
+        return e;
+    }
+    return hipSuccess;
+  };
+  const std::string key =
+      key_of("wsTrain", {(uint64_t)state, (uint64_t)X, (uint64_t)s_in, (uint64_t)c_star,
+                         (uint64_t)G, (uint64_t)m, (uint64_t)k, (uint64_t)x3, (uint64_t)b,
+                         (uint64_t)__builtin_bit_cast(uint32_t, lr), (uint64_t)perm_d,
+                         (uint64_t)ctr, (uint64_t)coef, (uint64_t)eacc, (uint64_t)B.Xb,
+                         (uint64_t)B.grads, (uint64_t)B.lrow, (uint64_t)B.A1, (uint64_t)B.dA});
   std::vector<int> perm(m);
-  int step = 0;
   for (int ep = 0; ep < epochs; ++ep) {
     // Fisher-Yates shuffle driven by the counter-based generator
     for (int64_t i = 0; i < m; ++i) perm[i] = (int)i;
-    const uint64_t key = sm_key(seed, 100 + ep);
+    const uint64_t key_ep = sm_key(seed, 100 + ep);
     for (int64_t i = m - 1; i > 0; --i) {
-      const uint64_t u = sm_mix(key + (uint64_t)(i + 1) * SM_GAMMA);
+      const uint64_t u = sm_mix(key_ep + (uint64_t)(i + 1) * SM_GAMMA);
       const int64_t j = (int64_t)(u % (uint64_t)(i + 1));
       std::swap(perm[i], perm[j]);
     }
+    HIP_TRY(hipMemcpyAsync(perm_d, perm.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+    HIP_TRY(run_graph(h, key, s, epoch));
     double ep_loss = 0.0;
-    int64_t nb = 0;
-    std::vector<double> lrow(b);
-    for (int64_t r0 = 0; r0 + b <= m; r0 += b) {
-      HIP_TRY(hipMemcpyAsync(B.idx, perm.data() + r0, sizeof(int) * b, hipMemcpyHostToDevice, s));
-      LAUNCH(NMF_K_OTHER, launch_gather(X, B.idx, b, WS_IN, B.Xb, s));
-      LAUNCH(NMF_K_OTHER, launch_gather(s_in, B.idx, b, 1, B.sb, s));
-      LAUNCH(NMF_K_OTHER, launch_gather(c_star, B.idx, b, k, B.cb, s));
-      ++step;
-      HIP_TRY(ws_forward(h, state, L, B.Xb, B.sb, b, k, x3, B, B.W, s));
-      HIP_TRY(ws_backward(h, state, L, B.Xb, B.sb, B.cb, G, b, k, x3, B, s));
-      LAUNCH(NMF_K_OTHER, launch_adam(state, B.grads, state + L.count, state + 2 * L.count,
-                                      L.count, lr, 0.9f, 0.999f, 1e-8f, step, s));
-      HIP_TRY(hipMemcpyAsync(lrow.data(), B.lrow, sizeof(double) * b, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      for (double v : lrow) ep_loss += v;
-      nb += b;
-    }
-    if (loss_hist) loss_hist[ep] = nb ? ep_loss / nb : 0.0;
+    HIP_TRY(hipMemcpyAsync(&ep_loss, eacc, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));  // also keeps perm alive for the copy
+    if (loss_hist) loss_hist[ep] = nb ? ep_loss / ((double)nb * b) : 0.0;
     if (!std::isfinite(ep_loss)) return fail(NMF_ERR_DIVERGED, "warm-start loss became non-finite");
   }
   HIP_TRY(hipStreamSynchronize(s));

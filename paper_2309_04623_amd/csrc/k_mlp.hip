@@ -186,6 +186,60 @@ __global__ void k_gather(const float* src, const int* idx, int rows, int n, floa
   out[i] = src[(int64_t)idx[r] * n + c];
 }
 
+// ---- training steps replayed from one captured graph ----------------------
+// The minibatch cursor, the Adam step t and the bias corrections
+// c1 = 1 - b1^t, c2 = 1 - b2^t live in device memory and advance on the
+// device after each step, so an epoch of steps is a fixed sequence of
+// launches.  ctr = {cursor, t}, coef = {c1, c2}.
+__global__ void k_gather_cur(const float* src, const int* perm, const int* ctr, int rows, int n,
+                             float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows * n) return;
+  const int r = (int)(i / n), c = (int)(i % n);
+  out[i] = src[(int64_t)perm[ctr[0] + r] * n + c];
+}
+
+__global__ void k_adam_dev(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                           float b1, float b2, float eps, const float* coef) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float c1 = coef[0], c2 = coef[1];
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_train_ctr(int* ctr, float* coef, int advance, int b, float b1, float b2) {
+  if (threadIdx.x != 0) return;
+  if (advance) {
+    ctr[0] += b;
+    ctr[1] += 1;
+  } else {
+    ctr[0] = 0;
+    ctr[1] = 1;
+  }
+  coef[0] = 1.f - powf(b1, (float)ctr[1]);
+  coef[1] = 1.f - powf(b2, (float)ctr[1]);
+}
+
+// acc (+)= sum of the b per-row loss terms, reduced in a fixed order.
+__global__ __launch_bounds__(256) void k_loss_accum(const double* lrow, int b, double* acc,
+                                                   int reset) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < b; i += 256) v += lrow[i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) acc[0] = reset ? red[0] : acc[0] + red[0];
+}
+
 // Masked-mean pooling of dense frames (F x ny*nx) to F x 1024 and the
 // per-frame masked mean s (1 when no pixel has weight or the mean is <= 0).
 __global__ __launch_bounds__(256) void k_pool(const float* T, const float* MT, int ny, int nx,
@@ -281,6 +335,26 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 hipError_t launch_gather(const float* src, const int* idx, int rows, int n, float* out,
                          hipStream_t st) {
   hipLaunchKernelGGL(k_gather, grid1((int64_t)rows * n), dim3(256), 0, st, src, idx, rows, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_gather_cur(const float* src, const int* perm, const int* ctr, int rows, int n,
+                             float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_cur, grid1((int64_t)rows * n), dim3(256), 0, st, src, perm, ctr,
+                     rows, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_adam_dev(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                           float b1, float b2, float eps, const float* coef, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam_dev, grid1(n), dim3(256), 0, st, p, g, m, v, n, lr, b1, b2, eps, coef);
+  return hipGetLastError();
+}
+hipError_t launch_train_ctr(int* ctr, float* coef, int advance, int b, float b1, float b2,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_train_ctr, dim3(1), dim3(64), 0, st, ctr, coef, advance, b, b1, b2);
+  return hipGetLastError();
+}
+hipError_t launch_loss_accum(const double* lrow, int b, double* acc, int reset, hipStream_t st) {
+  hipLaunchKernelGGL(k_loss_accum, dim3(1), dim3(256), 0, st, lrow, b, acc, reset);
   return hipGetLastError();
 }
 hipError_t launch_pool(const float* T, const float* MT, int f, int ny, int nx, float* X, float* s,

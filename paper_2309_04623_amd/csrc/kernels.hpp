@@ -271,6 +271,13 @@ hipError_t launch_sub(const float* a, const float* b, int64_t n, float* out, hip
 hipError_t launch_colsum(const float* d, int B, int N, float* out, hipStream_t st);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                        float b2, float eps, int t, hipStream_t st);
+hipError_t launch_gather_cur(const float* src, const int* perm, const int* ctr, int rows, int n,
+                             float* out, hipStream_t st);
+hipError_t launch_adam_dev(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                           float b1, float b2, float eps, const float* coef, hipStream_t st);
+hipError_t launch_train_ctr(int* ctr, float* coef, int advance, int b, float b1, float b2,
+                            hipStream_t st);
+hipError_t launch_loss_accum(const double* lrow, int b, double* acc, int reset, hipStream_t st);
 hipError_t launch_gather(const float* src, const int* idx, int rows, int n, float* out,
                          hipStream_t st);
 hipError_t launch_pool(const float* T, const float* MT, int f, int ny, int nx, float* X, float* s,

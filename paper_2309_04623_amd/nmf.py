@@ -25,6 +25,7 @@ NMF_WARN_NONMONOTONE, NMF_WARN_MAXITER = 1, 2
 PREC = {"fp32": 0, "bf16x3": 1}
 F_VALIDATE_DATA, F_CLIP_NEGATIVE, F_NORMALIZE_H = 1, 2, 4
 F_BINARY_WEIGHTS, F_MASKED_GRAM, F_WARM_START, F_ASYNC, F_AUTOTUNE = 8, 16, 32, 64, 128
+RS_WARM_FALLBACK = 1 << 8  # report status bit: a warm start fell back to the cold start
 
 MAT_W, MAT_H, MAT_C = 0, 1, 2
 
@@ -239,8 +240,13 @@ def objective(V, M, W, H, precision="fp32", handle=None) -> float:
 
 
 def build_basis(V, M, k, iters, *, precision="fp32", W_init=None, H_init=None, seed=0, flags=0,
-                eps=1e-30, split=0, tol=0.0, check_every=0, waves=0, pipeline=0, handle=None):
-    """Basis construction (Eq. 3 iterated).  Returns (W, H, J history, report)."""
+                eps=1e-30, split=0, tol=0.0, check_every=0, waves=0, pipeline=0, warm=False,
+                handle=None):
+    """Basis construction (Eq. 3 iterated).  Returns (W, H, J history, report).
+    ``warm=True``: (W_init, H_init) is a warm start kept only if its cost is
+    not above the seeded cold start's."""
+    if warm:
+        flags |= F_WARM_START
     torch = _torch()
     dev = V.device.index or 0
     h = handle or default_handle(dev)

@@ -206,3 +206,65 @@ def test_warm_start_falls_back_to_cold():
     assert np.array_equal(host(Cc)[1::2], host(Cw)[1::2])
     with pytest.raises(nmf.NmfError):
         nmf.project(dev(H), dev(T), dev(MT), 5, seed=2, C_init=dev(bad), warm=True)
+
+
+# ---- warm start of the basis build's component initialisation -------------
+
+def _library(Htrue, n, seed, ny, nx):
+    g = np.random.default_rng(seed)
+    clean = g.gamma(2.0, 1.0, (n, Htrue.shape[0])) @ Htrue
+    gain = 1e4 / clean.max(axis=1, keepdims=True)
+    V = g.poisson(gain * clean) / gain
+    M = (g.random(V.shape) > 0.02) * synth.mask_wedge(ny, nx, 6.0)[None, :]
+    return V.astype(np.float32), M.astype(np.float32)
+
+
+def test_basis_build_component_warm_start():
+    """Warm start of the component initialisation: a prior basis built on one
+    library, and for each image of a second library the coefficients that the
+    network (trained on the prior library's images and their projections on
+    that basis) predicts.  The warm build is kept (its cost is below the cold
+    start's, as the oracle's costs of both starts say), matches the oracle's
+    build from the same start, and after 25 iterations is below the cold
+    build's cost after 100.  A useless start falls back: the result is then
+    bitwise the cold build's."""
+    from oracle import nmf64, prng
+    ny = nx = 64
+    k, n, T = 10, 400, 100
+    p = ny * nx
+    g = np.random.default_rng(31)
+    Htrue = synth.components_speckle(g, 14, ny, nx)
+    V0, M0 = _library(Htrue, n, 1, ny, nx)
+    V1, M1 = _library(Htrue, n, 2, ny, nx)
+    say("component warm start: prior basis and training pairs")
+    _, Hp, _, _ = nmf.build_basis(dev(V0), dev(M0), k, 300, seed=3)
+    C0, _ = nmf.project(Hp, dev(V0), dev(M0), 3000, gram=True, seed=4)
+    X0, s0 = nmf.ws_pool(dev(V0), dev(M0), ny, nx)
+    Hh = host(Hp).astype(np.float64)
+    st = nmf.ws_init(k, seed=5)
+    say("component warm start: training")
+    hist = nmf.ws_train(st, X0, s0, C0, dev(Hh @ Hh.T), k, epochs=30, batch=64, lr=1e-3, seed=6)
+    assert np.all(np.isfinite(hist))
+    X1, s1 = nmf.ws_pool(dev(V1), dev(M1), ny, nx)
+    Wi = nmf.ws_infer(st, X1, s1, k)
+    say("component warm start: builds")
+    Ww, Hw, Jw, repw = nmf.build_basis(dev(V1), dev(M1), k, T, W_init=Wi, H_init=Hp, seed=7,
+                                       warm=True)
+    assert nmf.warm_fallbacks() == 0 and not (repw["status_flags"] & nmf.RS_WARM_FALLBACK)
+    Wc, Hc, Jc, _ = nmf.build_basis(dev(V1), dev(M1), k, T, seed=7)
+    Wih, Hph = host(Wi), host(Hp)
+    Wc0, Hc0 = prng.init_matrix(7, prng.MAT_W, n, k), prng.init_matrix(7, prng.MAT_H, k, p)
+    Vh = np.where(M1 > 0, V1, 0.0)
+    assert nmf64.objective(Vh, M1, Wih, Hph) <= nmf64.objective(Vh, M1, Wc0, Hc0)
+    Wo, Ho, Jo = nmf64.build_basis(V1, M1, Wih, Hph, T)
+    rel = np.abs(Jw - Jo) / Jo
+    print(f"  warm J {Jw[0]:.4e} -> {Jw[25]:.4e} (25) -> {Jw[T]:.4e}; cold J {Jc[25]:.4e} (25) "
+          f"-> {Jc[T]:.4e}; oracle max rel {rel.max():.2e}", flush=True)
+    assert rel.max() <= 1e-5
+    assert rel_model_err(M1, host(Ww) @ host(Hw), Wo @ Ho) <= 1e-4
+    assert Jw[25] < Jc[T]
+    bad = Wi.clone().fill_(1e3)
+    Wf, Hf, _, repf = nmf.build_basis(dev(V1), dev(M1), k, T, W_init=bad, H_init=Hp, seed=7,
+                                      warm=True)
+    assert nmf.warm_fallbacks() == 1 and repf["status_flags"] & nmf.RS_WARM_FALLBACK
+    assert np.array_equal(host(Wf), host(Wc)) and np.array_equal(host(Hf), host(Hc))
