@@ -14,11 +14,13 @@
 //     and shared through LDS;
 //   * every fetch is an LDS DMA (global_load_lds_dwordx4: each lane's 16
 //     bytes land in LDS without passing through registers), issued one row
-//     tile ahead into the other half of a double buffer: the next operand
-//     set by all waves, the next data (and weight) tile of each wave's column
-//     into that wave's own slot.  The only wait is the one before the
-//     barrier that closes each row tile, so the fetches overlap a whole
-//     tile of MFMA work and cost no registers;
+//     tile ahead into the other half of a double buffer, or, with bit-mask
+//     weights at KP = 128, two row tiles ahead into three buffers (the
+//     weight bits then travel by DMA too): the operand set by all waves, the
+//     data (and weight) tile of each wave's column into that wave's own
+//     slot.  The only wait is the one before the barrier that closes each
+//     row tile, so the fetches overlap whole tiles of MFMA work and cost no
+//     registers;
 //   * each wave keeps its column tile's right-factor operands and its
 //     num/den accumulators (2 * KP / 32 MFMA tiles) in registers (one wave
 //     per SIMD).
@@ -35,35 +37,44 @@ namespace nmf {
 constexpr int WIDE_NW = 4;  // waves (column tiles) per workgroup
 
 // LDS layout (bytes): [NB operand sets of KP * 256][per wave: NB data tiles
-// of 4 KB][per wave: NB weight tiles of 4 KB, FP32 weights when they fit],
-// NB = 3 for the cross-tile pipelined loop (KP <= 128), else 2.  The update
-// epilogue reuses the space from 0 to stage each wave's new 32 x KP tile.
+// of 4 KB][per wave: NB weight tiles of 4 KB, FP32 weights when they fit, or
+// NB bit tiles of 128 bytes in the three-buffer form], NB = 3 for the
+// cross-tile pipelined loop (KP <= 96) and the three-buffer form, else 2.
+// The update epilogue reuses the space from 0 to stage each wave's new
+// 32 x KP tile.
 constexpr int LDS_MAX = 160 * 1024 - 256;  // dynamic part (the static part holds 32 bytes)
 template <int KP>
 __host__ __device__ constexpr bool wide_xp() {
   return KP <= 96 && 3 * KP * 256 + WIDE_NW * 3 * 4096 <= LDS_MAX;
 }
-template <int KP>
+// Split-precision tiles without the cross-tile pipeline take three buffers
+// when they fit: fetches run two row tiles ahead.
+template <int KP, bool BIN>
+__host__ __device__ constexpr bool wide_tb() {
+  return BIN && !wide_xp<KP>() && 3 * KP * 256 + WIDE_NW * 3 * (4096 + 128) <= LDS_MAX;
+}
+template <int KP, bool BIN>
 __host__ __device__ constexpr int wide_nbuf() {
-  return wide_xp<KP>() ? 3 : 2;
+  return (wide_xp<KP>() || wide_tb<KP, BIN>()) ? 3 : 2;
 }
-template <int KP>
+template <int KP, bool BIN>
 __host__ __device__ constexpr int wide_ops_bytes() {
-  return wide_nbuf<KP>() * KP * 256;
+  return wide_nbuf<KP, BIN>() * KP * 256;
 }
-template <int KP>
+template <int KP, bool BIN>
 __host__ __device__ constexpr int wide_slot_bytes() {  // data (or weight) slots of all waves
-  return WIDE_NW * wide_nbuf<KP>() * 4096;
+  return WIDE_NW * wide_nbuf<KP, BIN>() * 4096;
 }
 // FP32 weight tiles go through LDS when they fit; otherwise they are loaded
 // into registers one step ahead.
 template <int KP, bool BIN>
 __host__ __device__ constexpr bool wide_mw_dma() {
-  return !BIN && wide_ops_bytes<KP>() + 2 * wide_slot_bytes<KP>() <= LDS_MAX;
+  return !BIN && wide_ops_bytes<KP, BIN>() + 2 * wide_slot_bytes<KP, BIN>() <= LDS_MAX;
 }
 template <int KP, bool BIN>
 __host__ __device__ constexpr int wide_lds_bytes() {
-  return wide_ops_bytes<KP>() + wide_slot_bytes<KP>() * (wide_mw_dma<KP, BIN>() ? 2 : 1);
+  return wide_ops_bytes<KP, BIN>() + wide_slot_bytes<KP, BIN>() * (wide_mw_dma<KP, BIN>() ? 2 : 1) +
+         (wide_tb<KP, BIN>() ? WIDE_NW * 3 * 128 : 0);
 }
 template <int KP>
 __host__ __device__ constexpr int wide_stage_bytes() {
@@ -73,6 +84,18 @@ __host__ __device__ constexpr int wide_stage_bytes() {
 // One LDS DMA of 16 bytes per lane: lane i's bytes land at lds + 16 i.
 __device__ __forceinline__ void dma16(const void* src, unsigned char* lds) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+// The same with 4 bytes per lane: lane i's bytes land at lds + 4 i.
+__device__ __forceinline__ void dma4(const void* src, unsigned char* lds) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+}
+
+// Places a register value at this point of the instruction stream: it is
+// computed before this point and, used as an input, not hoisted above it
+// (an empty statement on one register: no instruction, no memory access).
+template <class T>
+__device__ __forceinline__ void pin(T& x) {
+  asm volatile("" : "+v"(x));
 }
 
 template <int PREC, int KP, int MODE, bool BIN>
@@ -87,10 +110,10 @@ __global__ __launch_bounds__(64 * WIDE_NW, 1) void k_wide(DualArgs a) {
   constexpr int CV = NV / NCH;                    // vectors per chunk
   constexpr int ESZ = PREC == PREC_FP32 ? 4 : 2;  // bytes per element
   constexpr int OPS = KP * 256;                   // bytes per operand set
-  constexpr int NBUF = wide_nbuf<KP>();           // operand / data buffers
+  constexpr int NBUF = wide_nbuf<KP, BIN>();      // operand / data buffers
   constexpr bool XP = wide_xp<KP>();              // cross-tile pipelined loop
-  constexpr int DATA0 = wide_ops_bytes<KP>();     // data slots
-  constexpr int MW0 = DATA0 + wide_slot_bytes<KP>();  // weight slots (FP32 weights)
+  constexpr int DATA0 = wide_ops_bytes<KP, BIN>();  // data slots
+  constexpr int MW0 = DATA0 + wide_slot_bytes<KP, BIN>();  // weight slots (FP32 weights)
   constexpr bool MWD = wide_mw_dma<KP, BIN>();
   // operand reads pinned one MFMA group ahead of their use (beyond KP = 128
   // the pinned order runs out of registers and the compiler's order is kept)
@@ -366,7 +389,186 @@ __global__ __launch_bounds__(64 * WIDE_NW, 1) void k_wide(DualArgs a) {
       }
     }
   };
+  // Split-precision tile in an explicit instruction order, so that the
+  // vector work sits between independent matrix products (one wave per
+  // SIMD cannot hide it otherwise):
+  //   (1) Y = L Rt, operand reads two product groups ahead, with the RNE
+  //       split of A = Mw o D into bf16 hi/lo spread over the groups;
+  //   (2) num of rows 0-15 (lane half 0 of the reduction) beside Z = Mw o Y,
+  //       the objective terms and the split of Z for rows 0-15;
+  //   (3) den of rows 0-15 beside the same for rows 16-31;
+  //   (4) num, then den, of rows 16-31.
+  // Every accumulator receives its products in the order of the plain form
+  // and the objective terms are summed in element order (with bit-mask
+  // weights the results are the same bits); a weighted product is rounded
+  // to FP32 before it is split.  ``issue(s)`` is called at the start of
+  // product group s (s < KP / 16 + 3 * KP / 32) so that a caller can spread
+  // its memory fetches over the tile.
+  auto compute_x4 = [&](int buf, uint32_t mb, const f32x4(&wr)[4], auto&& issue) {
+    constexpr int NQ = KP / 16;
+    const unsigned char* base = smem + buf * OPS;
+    const f32x4* dp = reinterpret_cast<const f32x4*>(dslot + buf * 4096) + lane;
+    const f32x4* mp = reinterpret_cast<const f32x4*>(mslot + buf * 4096) + lane;
+    const bf16x8* Lh = reinterpret_cast<const bf16x8*>(base) + lane;
+    const bf16x8* Ll = Lh + CV;
+    const bf16x8* LTh = Lh + 2 * CV;
+    const bf16x8* LTl = Lh + 3 * CV;
+    bf16x8 lh[NQ], ll[NQ];
+    f32x4 dq[4], wq[4];
+    lh[0] = Lh[0];
+    ll[0] = Ll[0];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      dq[u] = dp[64 * u];
+      if constexpr (MWD) wq[u] = mp[64 * u];
+      else if constexpr (!BIN) wq[u] = wr[u];
+    }
+    lh[1] = Lh[64];
+    ll[1] = Ll[64];
+    __builtin_amdgcn_sched_barrier(0);
+    float dv[16], mv[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      dv[i] = dq[i >> 2][i & 3];
+      mv[i] = BIN ? 1.f : wq[i >> 2][i & 3];
+    }
+    uint32_t ahp[8], alp[8], zhp[8], zlp[8];
+    auto split2 = [](float x0, float x1, uint32_t& hi, uint32_t& lo) {
+      const f32x2 v = {x0, x1};
+      const bf16x2 h = __builtin_convertvector(v, bf16x2);
+      const bf16x2 l = __builtin_convertvector(v - __builtin_convertvector(h, f32x2), bf16x2);
+      hi = __builtin_bit_cast(uint32_t, h);
+      lo = __builtin_bit_cast(uint32_t, l);
+    };
+    auto pack = [](const uint32_t* p) {
+      typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+      const u32x4 v = {p[0], p[1], p[2], p[3]};
+      return __builtin_bit_cast(bf16x8, v);
+    };
+    bf16x8 th[MT], tl[MT];
+    // (1)
+    f32x16 y = zero16();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      if (q + 2 < NQ) {
+        lh[q + 2] = Lh[64 * (q + 2)];
+        ll[q + 2] = Ll[64 * (q + 2)];
+      }
+      if (q == NQ - 2) {  // the num/den operands of rows 0-15
+#pragma unroll
+        for (int t = 0; t < MT; ++t) tl[t] = LTl[64 * (2 * t)];
+      }
+      if (q == NQ - 1) {
+#pragma unroll
+        for (int t = 0; t < MT; ++t) th[t] = LTh[64 * (2 * t)];
+      }
+      issue(q);
+      y = mfma_bf16(ll[q], rth[q], y);
+      y = mfma_bf16(lh[q], rtl[q], y);
+      y = mfma_bf16(lh[q], rth[q], y);
+#pragma unroll
+      for (int pr = (8 * q) / NQ; pr < (8 * (q + 1)) / NQ; ++pr) {
+        float x0 = dv[2 * pr], x1 = dv[2 * pr + 1];
+        pin(x0);
+        pin(x1);
+        split2(__fmul_rn(mv[2 * pr], x0), __fmul_rn(mv[2 * pr + 1], x1), ahp[pr], alp[pr]);
+        pin(ahp[pr]);
+        pin(alp[pr]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const bf16x8 ah0 = pack(ahp), al0 = pack(alp), ah1 = pack(ahp + 4), al1 = pack(alp + 4);
+    float js = 0.f;
+    float zv[16];
+    auto elem = [&](int i) {
+      float yi = y[i];
+      pin(yi);
+      const float r = dv[i] - yi;
+      if constexpr (BIN) {
+        const int mk = (int)(mb << (31 - i)) >> 31;
+        zv[i] = __int_as_float(__float_as_int(yi) & mk);
+        const float rm = __int_as_float(__float_as_int(r) & mk);
+        js = fmaf(rm, rm, js);
+      } else {
+        zv[i] = __fmul_rn(mv[i], yi);
+        js = fmaf(mv[i] * r, r, js);
+      }
+      pin(zv[i]);
+      pin(js);
+    };
+    auto zsplit = [&](int i, int k) {
+      float z0 = zv[i], z1 = zv[i + 1];
+      pin(z0);
+      pin(z1);
+      split2(z0, z1, zhp[k], zlp[k]);
+      pin(zhp[k]);
+      pin(zlp[k]);
+    };
+    // (2) num, rows 0-15; element work 0-7 (one element or one pair split
+    // per product)
+#pragma unroll
+    for (int m = 0; m < 3 * MT; ++m) {
+      const int t = m % MT, s = m / MT;
+      issue(NQ + m);
+      if (s == 0) num[t] = mfma_bf16(tl[t], ah0, num[t]);
+      else if (s == 1) num[t] = mfma_bf16(th[t], al0, num[t]);
+      else num[t] = mfma_bf16(th[t], ah0, num[t]);
+      if (m < 8) elem(m);
+      else if (m < 12) zsplit(2 * (m - 8), m - 8);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (3 * MT < 12) {  // MT < 4: the rest of the element work of rows 0-15
+#pragma unroll
+      for (int m = 3 * MT; m < 12; ++m) {
+        if (m < 8) elem(m);
+        else zsplit(2 * (m - 8), m - 8);
+      }
+    }
+    const bf16x8 zh0 = pack(zhp), zl0 = pack(zlp);
+    // (3) den, rows 0-15; element work 8-15, and the operands of rows 16-31
+#pragma unroll
+    for (int m = 0; m < 3 * MT; ++m) {
+      const int t = m % MT, s = m / MT;
+      if (s == 0) den[t] = mfma_bf16(tl[t], zh0, den[t]);
+      else if (s == 1) den[t] = mfma_bf16(th[t], zl0, den[t]);
+      else den[t] = mfma_bf16(th[t], zh0, den[t]);
+      if (m < 8) elem(8 + m);
+      else if (m < 12) zsplit(8 + 2 * (m - 8), 4 + m - 8);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (3 * MT < 12) {
+#pragma unroll
+      for (int m = 3 * MT; m < 12; ++m) {
+        if (m < 8) elem(8 + m);
+        else zsplit(8 + 2 * (m - 8), 4 + m - 8);
+      }
+    }
+    jacc += (double)js;
+    const bf16x8 zh1 = pack(zhp + 4), zl1 = pack(zlp + 4);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      tl[t] = LTl[64 * (2 * t + 1)];
+      th[t] = LTh[64 * (2 * t + 1)];
+    }
+    // (4) rows 16-31
+#pragma unroll
+    for (int t = 0; t < MT; ++t) num[t] = mfma_bf16(tl[t], ah1, num[t]);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) den[t] = mfma_bf16(tl[t], zh1, den[t]);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) num[t] = mfma_bf16(th[t], al1, num[t]);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) den[t] = mfma_bf16(th[t], zl1, den[t]);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) num[t] = mfma_bf16(th[t], ah1, num[t]);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) den[t] = mfma_bf16(th[t], zh1, den[t]);
+  };
   auto compute = [&](int buf, uint32_t mb, const f32x4(&wr)[4]) {
+    if constexpr (PREC == PREC_BF16X3 && MODE != MODE_OBJ && KP <= 128) {
+      compute_x4(buf, mb, wr, [](int) {});
+      return;
+    }
     const f32x16 y = y_part(buf);
     if constexpr (RA) __builtin_amdgcn_sched_barrier(0);
     BOps B;
@@ -439,6 +641,68 @@ __global__ __launch_bounds__(64 * WIDE_NW, 1) void k_wide(DualArgs a) {
       if (tr + 2 >= t_end) break;
       step(tr + 2, 2, 0, 1, bC, wC, bA, wA);
     }
+  } else if constexpr (NBUF == 3) {
+    // Operand sets, data tiles and weight bits are fetched two row tiles
+    // ahead into three buffers.  The barrier closing step r waits only
+    // until the fetches of tile r + 2 (issued at the start of step r) are
+    // the ones in flight (memory loads complete in issue order), so
+    // everything tile r + 1 needs has landed.  The buffer they fill was last
+    // read in step r - 1, which every wave has left.
+    constexpr int NV_STEP = PT + 5;
+    static_assert(BIN && NV_STEP < 64, "three buffers take bit-mask weights");
+    // s_waitcnt: vmcnt <= NV_STEP, lgkmcnt 0, expcnt untouched
+    constexpr int WAIT_PREV = (NV_STEP & 15) | (7 << 4) | (0 << 8) | ((NV_STEP >> 4) << 14);
+    auto close_step = [&]() {
+      __builtin_amdgcn_s_waitcnt(WAIT_PREV);
+      __builtin_amdgcn_s_barrier();
+    };
+    unsigned char* bslot = smem + DATA0 + wide_slot_bytes<KP, BIN>() + wave * 3 * 128;
+    auto fetch_bits = [&](int t, int buf) {
+      if (lane < 32) dma4(bcol + (int64_t)t * 128 + lofs / 4, bslot + buf * 128);
+    };
+    const f32x4 wnone[4] = {};
+    if (tr < t_end) {
+      const int n1 = min(tr + 1, t_end - 1);
+      fetch_ops(tr, 0);
+      fetch_data(tr, 0);
+      fetch_bits(tr, 0);
+      fetch_ops(n1, 1);
+      fetch_data(n1, 1);
+      fetch_bits(n1, 1);
+    }
+    close_step();
+    int cur = 0;
+    for (; tr < t_end; ++tr) {
+      const int n2 = min(tr + 2, t_end - 1), buf2 = cur == 0 ? 2 : cur - 1;
+      const uint32_t mb = *reinterpret_cast<const uint16_t*>(bslot + cur * 128 + lane * 2);
+      if constexpr (PREC == PREC_BF16X3 && MODE != MODE_OBJ && KP <= 128) {
+        // the fetches of tile r + 2 spread over the tile's products, one
+        // load per product group, so that the memory pipeline never backs
+        // up into the instruction stream
+        const unsigned char* osrc = csrc + (int64_t)n2 * KP * 32 * ESZ + cl0 * 16;
+        unsigned char* odst = smem + buf2 * OPS + (chunk * CV + cl0) * 16;
+        compute_x4(cur, mb, wnone, [&](int piece) {
+          if (piece < PT) {
+            dma16(osrc + (lofs + LS * 16 * piece), odst + LS * 16 * piece);
+          } else if (piece < PT + 4) {
+            const int u = piece - PT;
+            dma16(dcol + (int64_t)n2 * 4096 + (lofs + u * 1024), dslot + buf2 * 4096 + u * 1024);
+          } else if (piece == PT + 4) {
+            fetch_bits(n2, buf2);
+          }
+        });
+      } else {
+        fetch_ops(n2, buf2);
+        fetch_data(n2, buf2);
+        fetch_bits(n2, buf2);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(cur, mb, wnone);
+      }
+      close_step();
+      cur = cur == 2 ? 0 : cur + 1;
+    }
+    // the fetches still in flight land in buffers the epilogue reuses
+    __syncthreads();
   } else {
     if (tr < t_end) {
       fetch_ops(tr, 0);
