@@ -223,6 +223,63 @@ def make_cfg3(n: int = 2000, ny: int = 224, nx: int = 288, k0: int = 120, frames
 
 
 # --------------------------------------------------------------------------
+# Projection set: frames modelled on a fixed seeded basis
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class ProjectionSet:
+    """Science frames (float32, F x P) and their weights for projection onto
+    the fixed basis H (float32, K x P)."""
+    ny: int
+    nx: int
+    H: np.ndarray
+    T: np.ndarray
+    MT: np.ndarray
+
+
+def projection_basis(k: int = 100, k0: int = 120, ny: int = 200, nx: int = 200,
+                     cfg: int = 5) -> np.ndarray:
+    """The k0 speckle components of the projection set (float64); the first
+    k are the basis the frames are modelled with."""
+    return components_speckle(rng(cfg, S_LIBRARY), k0, ny, nx)
+
+
+def make_projection_set(frames: int, k: int = 100, k0: int = 120, ny: int = 200, nx: int = 200,
+                        cfg: int = 5, sub: int = 0, comps: np.ndarray | None = None,
+                        chunk: int = 512) -> ProjectionSet:
+    """STIS-shaped frames to be modelled on a fixed K-component basis: each
+    frame is a Poisson-like realisation (1e6 counts at its peak) of a
+    Gamma(2,1) mixture of k0 >= k speckle components, the basis and k0 - k
+    more (so frames lie near, not in, the span of the basis); every other
+    frame carries an inclined ring disk at 1e-3 of its stellar flux.  The
+    weights are mask / (T + 0.01) with the 12 px diagonal wedge and 1% bad
+    pixels per frame.  ``sub`` selects independent frame streams over the
+    same components."""
+    comps = projection_basis(k, k0, ny, nx, cfg) if comps is None else comps
+    p = ny * nx
+    gs, gd, gm = rng(cfg, S_SCIENCE, sub), rng(cfg, S_DISK, sub), rng(cfg, S_MASK, sub)
+    wedge = mask_wedge(ny, nx, 6.0)
+    dy, dx, _ = radius_grid(ny, nx)
+    T = np.empty((frames, p), np.float32)
+    MT = np.empty((frames, p), np.float32)
+    for c0 in range(0, frames, chunk):
+        n = min(chunk, frames - c0)
+        clean = gs.gamma(2.0, 1.0, size=(n, k0)) @ comps
+        for i in range(c0 % 2 == 0, n, 2):  # odd frames carry a disk
+            inc, pa = math.radians(gd.uniform(30.0, 80.0)), math.radians(gd.uniform(0.0, 180.0))
+            u = dx * math.cos(pa) + dy * math.sin(pa)
+            v = (-dx * math.sin(pa) + dy * math.cos(pa)) / max(math.cos(inc), 1e-3)
+            ring = np.exp(-0.5 * ((np.hypot(u, v) - 50.0) / 3.0) ** 2).reshape(-1)
+            clean[i] += ring * (1e-3 * clean[i].sum() / ring.sum())
+        gain = 1e6 / clean.max(axis=1, keepdims=True)
+        t = gs.poisson(gain * clean) / gain
+        T[c0:c0 + n] = t
+        keep = wedge[None, :] & (gm.random((n, p)) >= 0.01)
+        MT[c0:c0 + n] = np.where(keep, 1.0 / (t + 0.01), 0.0)
+    return ProjectionSet(ny, nx, comps[:k].astype(np.float32), T, MT)
+
+
+# --------------------------------------------------------------------------
 # Ragged frames (batched projection)
 # --------------------------------------------------------------------------
 

@@ -17,11 +17,22 @@ test, so it runs here once and the expected values are stored:
 * ``v_sha``, ``m_sha`` : SHA-256 of the float32 inputs, so a test can tell
                  that it generated the same library.
 
-Usage:  python tests/golden/make_oracle_fixtures.py {stis|miri} [out.npz]
+For the projection-to-tolerance measurement it stores the exact weighted
+NNLS coefficients (``oracle.nnls``) of a sample of frames:
+
+* ``w_star``   : the NNLS minimiser of the first ``n_sample`` frames of the
+                 1024-frame projection set (K = 100, FP64, from the normal
+                 equations by a Cholesky-reduced active-set solve);
+* ``kkt``      : each solution's KKT residual (a check that it is optimal);
+* ``h_sha``, ``t_sha``, ``m_sha`` : SHA-256 of the float32 basis and of the
+                 sample's frames and weights.
+
+Usage:  python tests/golden/make_oracle_fixtures.py {stis|miri|proj} [out.npz]
   stis: 500 images of 200 x 200 px, K = 30, 1000 iterations, weights
         mask / (V + 0.01) (seed 1)
   miri: 2000 images of 224 x 288 px, K = 100, 500 iterations, binary
         weights (seed 1)
+  proj: the first 256 of 1024 STIS-shaped frames on the seeded K = 100 basis
 """
 from __future__ import annotations
 
@@ -35,7 +46,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import nmf64, prng  # noqa: E402
+from oracle import nmf64, nnls, prng  # noqa: E402
 from paper_2309_04623_amd import synth  # noqa: E402
 
 CASES = {
@@ -51,8 +62,34 @@ def sha(x: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(x, np.float32).tobytes()).hexdigest()
 
 
+PROJ_FRAMES, PROJ_SAMPLE = 1024, 256
+
+
+def main_proj(out):
+    ps = synth.make_projection_set(PROJ_FRAMES)
+    H = ps.H.astype(np.float64)
+    W, kkt = [], []
+    t0 = time.time()
+    for f in range(PROJ_SAMPLE):
+        G, b, _ = nnls.normal_equations(H, ps.T[f], ps.MT[f])
+        w = nnls.nnls_gram(G, b)
+        W.append(w)
+        kkt.append(nnls.kkt_residual(G, b, w))
+        if f % 32 == 31:
+            print(f"proj: {f + 1}/{PROJ_SAMPLE} frames, max KKT residual {max(kkt):.1e} "
+                  f"({time.time() - t0:.0f} s)", flush=True)
+    np.savez_compressed(out, w_star=np.array(W), kkt=np.array(kkt), n_sample=PROJ_SAMPLE,
+                        n_frames=PROJ_FRAMES, h_sha=sha(ps.H), t_sha=sha(ps.T[:PROJ_SAMPLE]),
+                        m_sha=sha(ps.MT[:PROJ_SAMPLE]))
+    print(f"wrote {out}", flush=True)
+
+
 def main():
     name = sys.argv[1]
+    if name == "proj":
+        main_proj(sys.argv[2] if len(sys.argv) > 2 else os.path.join(
+            os.path.dirname(os.path.abspath(__file__)), "oracle_nnls_proj_k100.npz"))
+        return
     out = sys.argv[2] if len(sys.argv) > 2 else os.path.join(
         os.path.dirname(os.path.abspath(__file__)), f"oracle_{name}_fullsize.npz")
     c = CASES[name]

@@ -486,3 +486,29 @@ def test_projection_stop_rule_warm_restart():
     C, its, fb = nmf64.project_gram_tol(Tr, Mr, Hr, near, 20, 5, 1e-14, C_cold=Cc)
     assert np.all(fb == 2) and np.all(its == 40)
     assert np.allclose(C, nmf64.project_gram(Tr, Mr, Hr, Cc, 20), rtol=1e-12, atol=0)
+
+
+def test_stored_nnls_solutions_of_the_projection_set():
+    """The stored exact NNLS solutions used to judge projections to the 1e-4
+    tolerance are what the generator's frames give: same input bytes, and on
+    a few re-solved frames the same minimiser, optimal by its KKT
+    conditions and by the active-set route on the square-root-weighted
+    system (an independent solve)."""
+    import hashlib
+    import os
+    from paper_2309_04623_amd import synth
+    z = np.load(os.path.join(os.path.dirname(__file__), "golden", "oracle_nnls_proj_k100.npz"))
+    n_s = int(z["n_sample"])
+    ps = synth.make_projection_set(int(z["n_frames"]))
+    sha = lambda x: hashlib.sha256(np.ascontiguousarray(x, np.float32).tobytes()).hexdigest()
+    assert sha(ps.H) == str(z["h_sha"])
+    assert sha(ps.T[:n_s]) == str(z["t_sha"]) and sha(ps.MT[:n_s]) == str(z["m_sha"])
+    assert np.max(z["kkt"]) < 1e-10
+    for f in (0, 101, n_s - 1):
+        G, b, c = nnls.normal_equations(ps.H, ps.T[f], ps.MT[f])
+        w = z["w_star"][f]
+        assert nnls.kkt_residual(G, b, w) < 1e-10
+        ws = nnls.nnls_scipy(ps.H, ps.T[f], ps.MT[f])
+        assert nnls.cost(G, b, c, ws) >= nnls.cost(G, b, c, w) * (1 - 1e-9)
+        dm = np.sqrt((ws - w) @ G @ (ws - w) / (w @ G @ w))
+        assert dm < 1e-6, dm
