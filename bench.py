@@ -432,7 +432,7 @@ def tolerance_leg(args, nmf, synth, h, torch):
         r = None
         for tau in TAUS:
             r = gram_run(tau, **kw)
-            log(f"{label}: tol {tau:.0e}: met {r['met_fraction']:.3f}, {r['seconds']:.3f} s, "
+            log(f"{label}: tol {tau:.1e}: met {r['met_fraction']:.3f}, {r['seconds']:.3f} s, "
                 f"mean iterations {r['iterations_mean']:.0f}")
             if r["met_fraction"] >= 0.99:
                 break

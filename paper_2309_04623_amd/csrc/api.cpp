@@ -717,6 +717,16 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   const int ce = (c.prm->tol > 0.0 && c.prm->check_every > 0) ? c.prm->check_every : 0;
   int* its = nullptr;
   if (ce && (rc = ws(h, "giters", (size_t)c.f, &its))) return rc;
+  // K <= 128: two launches, G formed by workgroups of four waves, then
+  // iterated by small workgroups that keep a row of G per lane (several
+  // frames per compute unit)
+  const bool two_phase = KP <= 128;
+  float *Gf = nullptr, *cf = nullptr;
+  double* bf = nullptr;
+  if (two_phase && ((rc = ws(h, "gG", (size_t)c.f * K * K, &Gf)) ||
+                    (rc = ws(h, "gb", (size_t)c.f * KP, &bf)) ||
+                    (rc = ws(h, "gc", (size_t)c.f * KP, &cf))))
+    return rc;
   GramArgs a{};
   a.HT = Hf.m;
   a.K = K;
@@ -746,6 +756,9 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   a.check_every = ce;
   a.tol2 = ce ? c.prm->tol * c.prm->tol : 0.0;
   a.iters_out = its;
+  a.Gf = Gf;
+  a.bf = bf;
+  a.cf = cf;
   const FactorFillArgs fa = fill_args(Hf, c.H, 1, 0, 1, K);
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     hipError_t e;
@@ -756,7 +769,11 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
         (e = timed(h, NMF_K_OTHER, s,
                    [&]() { return launch_frame_order(c.offsets, a.F, order, sort_tmp, s); })))
       return e;
-    return timed(h, NMF_K_PROJECT, s, [&]() { return launch_gram(KP, ragged, a, 0, s, nullptr); });
+    if ((e = timed(h, NMF_K_PROJECT, s,
+                   [&]() { return launch_gram(KP, ragged, a, 0, s, nullptr, two_phase); })))
+      return e;
+    if (!two_phase) return hipSuccess;
+    return timed(h, NMF_K_PROJECT, s, [&]() { return launch_gram_iter(KP, a, s); });
   };
   const std::string key =
       key_of(ragged ? "gramR" : "gramD",
@@ -768,7 +785,7 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
               (uint64_t)__builtin_bit_cast(uint32_t, c.prm->floor_eps), (uint64_t)ce,
               __builtin_bit_cast(uint64_t, a.tol2), (uint64_t)its, (uint64_t)Hf.m,
               (uint64_t)queue, (uint64_t)stat, (uint64_t)order, (uint64_t)sort_tmp,
-              (uint64_t)fb});
+              (uint64_t)fb, (uint64_t)Gf, (uint64_t)bf, (uint64_t)cf});
   HIP_TRY(hipEventRecord(h->ev0, s));
   HIP_TRY(run_graph(h, key, s, enqueue));
   HIP_TRY(hipEventRecord(h->ev1, s));

@@ -56,8 +56,9 @@ __host__ __device__ constexpr int gram_stage_floats(int prec) {
   return 32 * KP + 64 + (prec == PREC_BF16X3 ? 4 * KP * GT_STRIDE : 0);
 }
 
-template <int KP, bool RAGGED, int PREC>
+template <int KP, bool RAGGED, int PREC, bool FORM>
 __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
+  static_assert(!FORM || KP <= 128, "the two-phase form keeps a row of G per lane");
   extern __shared__ __align__(16) float lds[];
   __shared__ int qslot;
   __shared__ double wsel[2][gram_waves<KP>()];
@@ -329,6 +330,19 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       __syncthreads();
     }
 
+    if constexpr (FORM) {
+      // hand G, b and the start over to the iterating launch
+      float* Go = a.Gf + (int64_t)f * K * K;
+      for (int x = tid; x < K * K; x += NTH) Go[x] = G[x];
+      if (tid < KP) {
+        a.bf[(int64_t)f * KP + tid] = bsh[tid];
+        a.cf[(int64_t)f * KP + tid] = csh[tid];
+      }
+      if (a.ticks && tid == 0) a.ticks[2 * (int64_t)f] = tick0;
+      __syncthreads();  // LDS is reused by the next frame
+      continue;
+    }
+
     // ---- iterations: (c G)_j with row j of G in registers (K <= 128) or
     // read from LDS (consecutive j across lanes, conflict-free) ------------
     // Optional per-frame stop rule: every check_every iterations the model
@@ -343,8 +357,8 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
     const f32x4* d4 = reinterpret_cast<const f32x4*>(dsh);
     const int ce = a.check_every;
     __shared__ int run_sh[2];  // iterations run, rule met
-    float g[KP <= 128 ? KP : 1];
-    if constexpr (KP <= 128) {
+    float g[(KP <= 128 && !FORM) ? KP : 1];
+    if constexpr (KP <= 128 && !FORM) {
 #pragma unroll
       for (int i = 0; i < KP; ++i) g[i] = (j < K && i < K) ? G[j * K + i] : 0.f;
     }
@@ -352,7 +366,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
     // (v G)_j for a vector v in LDS
     auto matvec = [&](const float* v, const f32x4* v4) -> float {
       float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
-      if constexpr (KP <= 128) {
+      if constexpr (KP <= 128 && !FORM) {
 #pragma unroll
         for (int i4 = 0; i4 < KQ; ++i4) {
           const f32x4 cv = v4[i4];
@@ -481,10 +495,10 @@ size_t gram_lds_bytes(int K, int KP, int prec) {
   return (size_t)goff * 4 + (size_t)KP * 8 + (size_t)KP * 4 * 2;  // G | b | c, d
 }
 
-template <int KP, bool RAGGED, int PREC>
+template <int KP, bool RAGGED, int PREC, bool FORM>
 static hipError_t gram_launch(const GramArgs& a, int max_blocks, hipStream_t s, int* grid_out) {
   const size_t lds = gram_lds_bytes(a.K, KP, PREC);
-  auto fn = k_gram<KP, RAGGED, PREC>;
+  auto fn = k_gram<KP, RAGGED, PREC, FORM>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -502,27 +516,172 @@ static hipError_t gram_launch(const GramArgs& a, int max_blocks, hipStream_t s, 
   return hipGetLastError();
 }
 
-template <bool RAGGED, int PREC>
+template <bool RAGGED, int PREC, bool FORM>
 static hipError_t gram_kp(int kp, const GramArgs& a, int max_blocks, hipStream_t s, int* g) {
   switch (kp) {
-    case 32: return gram_launch<32, RAGGED, PREC>(a, max_blocks, s, g);
-    case 64: return gram_launch<64, RAGGED, PREC>(a, max_blocks, s, g);
-    case 96: return gram_launch<96, RAGGED, PREC>(a, max_blocks, s, g);
-    case 128: return gram_launch<128, RAGGED, PREC>(a, max_blocks, s, g);
-    case 160: return gram_launch<160, RAGGED, PREC>(a, max_blocks, s, g);
-    case 192: return gram_launch<192, RAGGED, PREC>(a, max_blocks, s, g);
-    case 224: return gram_launch<224, RAGGED, PREC>(a, max_blocks, s, g);
-    default: return hipErrorInvalidValue;
+    case 32: return gram_launch<32, RAGGED, PREC, FORM>(a, max_blocks, s, g);
+    case 64: return gram_launch<64, RAGGED, PREC, FORM>(a, max_blocks, s, g);
+    case 96: return gram_launch<96, RAGGED, PREC, FORM>(a, max_blocks, s, g);
+    case 128: return gram_launch<128, RAGGED, PREC, FORM>(a, max_blocks, s, g);
+    default: break;
   }
+  if constexpr (!FORM) {
+    switch (kp) {
+      case 160: return gram_launch<160, RAGGED, PREC, false>(a, max_blocks, s, g);
+      case 192: return gram_launch<192, RAGGED, PREC, false>(a, max_blocks, s, g);
+      case 224: return gram_launch<224, RAGGED, PREC, false>(a, max_blocks, s, g);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <bool FORM>
+static hipError_t gram_form(int kp, bool ragged, const GramArgs& a, int max_blocks, hipStream_t s,
+                            int* grid_out) {
+  if (a.prec == PREC_BF16X3)
+    return ragged ? gram_kp<true, PREC_BF16X3, FORM>(kp, a, max_blocks, s, grid_out)
+                  : gram_kp<false, PREC_BF16X3, FORM>(kp, a, max_blocks, s, grid_out);
+  return ragged ? gram_kp<true, PREC_FP32, FORM>(kp, a, max_blocks, s, grid_out)
+                : gram_kp<false, PREC_FP32, FORM>(kp, a, max_blocks, s, grid_out);
 }
 
 hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, hipStream_t s,
-                       int* grid_out) {
-  if (a.prec == PREC_BF16X3)
-    return ragged ? gram_kp<true, PREC_BF16X3>(kp, a, max_blocks, s, grid_out)
-                  : gram_kp<false, PREC_BF16X3>(kp, a, max_blocks, s, grid_out);
-  return ragged ? gram_kp<true, PREC_FP32>(kp, a, max_blocks, s, grid_out)
-                : gram_kp<false, PREC_FP32>(kp, a, max_blocks, s, grid_out);
+                       int* grid_out, bool form) {
+  return form ? gram_form<true>(kp, ragged, a, max_blocks, s, grid_out)
+              : gram_form<false>(kp, ragged, a, max_blocks, s, grid_out);
+}
+
+// ---------------------------------------------------------------------------
+// Iterations of the two-phase form (K <= 128): one frame per workgroup of
+// one wave (KP <= 64) or two.  Thread j keeps row j of the frame's G in
+// registers and updates coefficient j; the coefficients travel through a
+// double buffer in LDS, so one barrier per iteration suffices (iteration t
+// reads buffer t % 2 and writes the other).  The arithmetic is that of the
+// combined kernel (same products, sums and FP64 update), so the two forms
+// give the same bits; they differ only in how many frames a compute unit
+// iterates at once (several small workgroups instead of one large one).
+// ---------------------------------------------------------------------------
+template <int KP>
+__global__ __launch_bounds__(KP <= 64 ? 64 : 128) void k_gram_iter(GramArgs a) {
+  constexpr int NT = KP <= 64 ? 64 : 128;
+  constexpr int NW = NT / 64;
+  constexpr int KQ = KP / 4;
+  __shared__ __align__(16) float cb[2][KP];
+  __shared__ __align__(16) float dsh[KP];
+  __shared__ double wsel[2][NW];
+  const int f = blockIdx.x;
+  if (f >= a.F) return;
+  const int K = a.K;
+  const int j = threadIdx.x, wave = j >> 6, lane = j & 63;
+  const uint64_t key = sm_key(a.seed, 2);
+  float g[KP];
+  const float* Gr = a.Gf + (int64_t)f * K * K + (j < K ? j : 0) * K;
+#pragma unroll
+  for (int i = 0; i < KP; ++i) g[i] = (j < K && i < K) ? Gr[i] : 0.f;
+  const double bj = j < KP ? a.bf[(int64_t)f * KP + j] : 0.0;
+  const bool warm_kept = a.warm && a.fallback && a.fallback[f] == 0;
+  const int ce = a.check_every;
+  auto sync = [&]() {
+    if constexpr (NW == 1) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();
+    }
+  };
+  auto matvec = [&](const float* v) -> float {
+    const f32x4* v4 = reinterpret_cast<const f32x4*>(v);
+    float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+#pragma unroll
+    for (int i4 = 0; i4 < KQ; ++i4) {
+      const f32x4 cv = v4[i4];
+      d0 = fmaf(cv[0], g[4 * i4 + 0], d0);
+      d1 = fmaf(cv[1], g[4 * i4 + 1], d1);
+      d2 = fmaf(cv[2], g[4 * i4 + 2], d2);
+      d3 = fmaf(cv[3], g[4 * i4 + 3], d3);
+    }
+    return (d0 + d1) + (d2 + d3);
+  };
+  // a sum over all coefficients, the same value in every thread: per wave
+  // in a fixed order, then the waves in order
+  auto block_sum2 = [&](double x1, double x2, double& s1, double& s2) {
+    x1 = wave_sum(x1);
+    x2 = wave_sum(x2);
+    if constexpr (NW == 1) {
+      s1 = x1;
+      s2 = x2;
+    } else {
+      if (lane == 0) {
+        wsel[0][wave] = x1;
+        wsel[1][wave] = x2;
+      }
+      __syncthreads();
+      s1 = 0.0;
+      s2 = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        s1 += wsel[0][w];
+        s2 += wsel[1][w];
+      }
+      __syncthreads();
+    }
+  };
+  float cj = j < KP ? a.cf[(int64_t)f * KP + j] : 0.f;
+  int its_total = 0;
+  bool met = false;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      // the warm start missed the rule by the cap: cold start, same cap
+      if (!(warm_kept && ce > 0 && !met)) break;
+      cj = j < K ? sm_uniform(key, (uint64_t)f * K + j) : 0.f;
+      if (j == 0) a.fallback[f] = 2;
+    }
+    if (j < KP) cb[0][j] = cj;
+    sync();
+    float cp = cj;
+    int it = 0;
+    bool stop = false;
+    for (; it < a.iters; ++it) {
+      const float* cur = cb[it & 1];
+      const float den = matvec(cur);
+      if (ce > 0 && it > 0 && it % ce == 0) {
+        const float dj = j < K ? cj - cp : 0.f;
+        if (j < KP) dsh[j] = dj;
+        sync();
+        const float dg = matvec(dsh);
+        double s1, s2;
+        block_sum2(j < K ? (double)dj * (double)dg : 0.0, j < K ? (double)cj * (double)den : 0.0,
+                   s1, s2);
+        if (s1 <= a.tol2 * s2) {  // the same value in every thread
+          stop = true;
+          break;
+        }
+        cp = cj;
+      }
+      if (j < K) cj = mu_apply_d(cj, bj, (double)den, a.eps);
+      if (j < KP) cb[(it + 1) & 1][j] = cj;
+      sync();
+    }
+    its_total += it;
+    met = stop;
+  }
+  if (a.iters_out && j == 0) a.iters_out[f] = its_total;
+  if (j < K) a.C_out[(int64_t)f * K + j] = cj;
+  if (a.ticks && j == 0) a.ticks[2 * (int64_t)f + 1] = wall_clock64();
+}
+
+hipError_t launch_gram_iter(int kp, const GramArgs& a, hipStream_t s) {
+  if (a.F <= 0) return hipSuccess;
+  switch (kp) {
+    case 32: hipLaunchKernelGGL(k_gram_iter<32>, dim3(a.F), dim3(64), 0, s, a); break;
+    case 64: hipLaunchKernelGGL(k_gram_iter<64>, dim3(a.F), dim3(64), 0, s, a); break;
+    case 96: hipLaunchKernelGGL(k_gram_iter<96>, dim3(a.F), dim3(128), 0, s, a); break;
+    case 128: hipLaunchKernelGGL(k_gram_iter<128>, dim3(a.F), dim3(128), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

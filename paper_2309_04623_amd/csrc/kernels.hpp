@@ -218,10 +218,20 @@ struct GramArgs {
   int check_every;
   double tol2;
   int* iters_out;      // nullable: iterations run per frame
+  // two-phase form (K <= 128): the forming launch writes each frame's G
+  // (K x K FP32), b (KP FP64) and starting coefficients (KP FP32) here, the
+  // iterating launch reads them
+  float* Gf;
+  double* bf;
+  float* cf;
 };
 size_t gram_lds_bytes(int K, int KP, int prec);
+// form = true: the launch only forms G, b and the start of every frame
+// (Gf, bf, cf; warm-start decision included); launch_gram_iter then runs
+// the iterations, one frame per workgroup of one (KP <= 64) or two waves.
 hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, hipStream_t s,
-                       int* grid_out);
+                       int* grid_out, bool form = false);
+hipError_t launch_gram_iter(int kp, const GramArgs& a, hipStream_t s);
 // Longest-first processing order of CSR frames (equal sizes by index): a
 // bitonic sort in LDS up to MAX_SORT_FRAMES frames, a radix sort over
 // ``tmp`` (4 f ints of device scratch) beyond.
