@@ -192,7 +192,8 @@ def main():
     def step(prec):
         W, H, J, rep = nmf.build_basis(V, M, K, iters, precision=prec, seed=1, flags=flags,
                                        handle=h)
-        C, _ = nmf.project(H, T, MT, W_["proj_iters"], seed=2, gram=True, flags=flags, handle=h)
+        C, _ = nmf.project(H, T, MT, W_["proj_iters"], seed=2, gram=True, flags=flags,
+                           precision=prec, handle=h)
         model, resid = nmf.subtract(H, C, T, MT, handle=h)
         return J, rep
 
