@@ -256,6 +256,15 @@ int64_t nmf_warm_fallbacks(nmf_handle h);
  * ran), NMF_ERR_ARG when f is smaller than the count. */
 int64_t nmf_frame_iters(nmf_handle h, int32_t* iters_out, int64_t f);
 
+/* How many times the persistent launch of the last synchronous masked-Gram
+ * projection on h took each frame from its work queue (1 for every frame
+ * when the queue is sound; a check of the batched form, Sec. 4.1 target
+ * modelling frame by frame).  visits_out: [host] room for f int32, or NULL
+ * to ask for the count only.  Returns that call's frame count (written
+ * unless visits_out is NULL), 0 when no masked-Gram projection ran on h,
+ * NMF_ERR_ARG when f is smaller than the count. */
+int64_t nmf_frame_visits(nmf_handle h, int32_t* visits_out, int64_t f);
+
 /* Frequency (kHz) of the device clock used by frame_ticks. */
 double nmf_device_clock_khz(nmf_handle h);
 

@@ -78,6 +78,7 @@ struct nmf_handle_s {
   std::unordered_map<std::string, Tuned> tuned;
   int64_t last_fallbacks = -1;  // frames of the last warm start that fell back
   std::vector<int32_t> last_frame_iters;  // of the last Gram projection with a stop rule
+  std::vector<int32_t> last_frame_visits;  // of the last Gram projection
 };
 
 namespace {
@@ -717,6 +718,8 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   const int ce = (c.prm->tol > 0.0 && c.prm->check_every > 0) ? c.prm->check_every : 0;
   int* its = nullptr;
   if (ce && (rc = ws(h, "giters", (size_t)c.f, &its))) return rc;
+  int* visits = nullptr;
+  if ((rc = ws(h, "gvisits", (size_t)c.f, &visits))) return rc;
   // K <= 128: two launches, G formed by workgroups of four waves, then
   // iterated by small workgroups that keep a row of G per lane (several
   // frames per compute unit)
@@ -759,11 +762,14 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   a.Gf = Gf;
   a.bf = bf;
   a.cf = cf;
+  a.visits = visits;
   const FactorFillArgs fa = fill_args(Hf, c.H, 1, 0, 1, K);
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     hipError_t e;
     if ((e = timed(h, NMF_K_OTHER, s, [&]() { return launch_set_int(queue, 0, s); }))) return e;
     if ((e = timed(h, NMF_K_OTHER, s, [&]() { return launch_set_int(stat, 0, s); }))) return e;
+    if ((e = timed(h, NMF_K_OTHER, s, [&]() { return launch_fill_int(visits, a.F, 0, s); })))
+      return e;
     if ((e = timed(h, NMF_K_OTHER, s, [&]() { return launch_factor_fill(fa, s); }))) return e;
     if (sorted &&
         (e = timed(h, NMF_K_OTHER, s,
@@ -785,7 +791,7 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
               (uint64_t)__builtin_bit_cast(uint32_t, c.prm->floor_eps), (uint64_t)ce,
               __builtin_bit_cast(uint64_t, a.tol2), (uint64_t)its, (uint64_t)Hf.m,
               (uint64_t)queue, (uint64_t)stat, (uint64_t)order, (uint64_t)sort_tmp,
-              (uint64_t)fb, (uint64_t)Gf, (uint64_t)bf, (uint64_t)cf});
+              (uint64_t)fb, (uint64_t)Gf, (uint64_t)bf, (uint64_t)cf, (uint64_t)visits});
   HIP_TRY(hipEventRecord(h->ev0, s));
   HIP_TRY(run_graph(h, key, s, enqueue));
   HIP_TRY(hipEventRecord(h->ev1, s));
@@ -806,6 +812,9 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   // With a stop rule: iterations per frame (a warm start restarted cold
   // counts both runs); a frame that ran to the cap of its last run did not
   // meet the rule.
+  h->last_frame_visits.resize((size_t)c.f);
+  HIP_TRY(hipMemcpy(h->last_frame_visits.data(), visits, (size_t)c.f * sizeof(int),
+                    hipMemcpyDeviceToHost));
   int iters_run = c.prm->max_iter, unmet = 0;
   h->last_frame_iters.clear();
   if (ce) {
@@ -1331,6 +1340,15 @@ int64_t nmf_frame_iters(nmf_handle h, int32_t* iters_out, int64_t f) {
   if (!have || !iters_out) return have;
   if (f < have) return fail(NMF_ERR_ARG, "iters_out must hold every frame");
   std::copy(h->last_frame_iters.begin(), h->last_frame_iters.end(), iters_out);
+  return have;
+}
+
+int64_t nmf_frame_visits(nmf_handle h, int32_t* visits_out, int64_t f) {
+  if (!h) return fail(NMF_ERR_ARG, "handle is NULL");
+  const int64_t have = (int64_t)h->last_frame_visits.size();
+  if (!have || !visits_out) return have;
+  if (f < have) return fail(NMF_ERR_ARG, "visits_out must hold every frame");
+  std::copy(h->last_frame_visits.begin(), h->last_frame_visits.end(), visits_out);
   return have;
 }
 

@@ -283,6 +283,18 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_fill_int(int* p, int64_t n, int v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = v;
+}
+
+hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_fill_int, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Basis normalisation: H_k <- H_k / ||H_k||, W[:, k] <- W[:, k] ||H_k||
 // ---------------------------------------------------------------------------

@@ -108,6 +108,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
     if (qi >= a.F) break;
     const int f = a.order ? a.order[qi] : qi;
     const uint64_t tick0 = wall_clock64();
+    if (a.visits && tid == 0) atomicAdd(a.visits + f, 1);
 
     int64_t s = 0, e = a.P;
     if constexpr (RAGGED) {

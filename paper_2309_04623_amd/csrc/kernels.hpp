@@ -111,6 +111,7 @@ struct FinishArgs {
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
 
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
+hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s);
 
 // Layout fill of a factor: from a user matrix (rows x K, row-major, or
 // K x rows if ``user_is_kxr``), or from the seeded generator when src is
@@ -224,6 +225,7 @@ struct GramArgs {
   float* Gf;
   double* bf;
   float* cf;
+  int* visits;  // nullable: per frame, incremented each time a workgroup takes it
 };
 size_t gram_lds_bytes(int K, int KP, int prec);
 // form = true: the launch only forms G, b and the start of every frame

@@ -76,6 +76,7 @@ _SIGS = {
     "nmf_device_clock_khz": (ctypes.c_double, [_vp]),
     "nmf_warm_fallbacks": (ctypes.c_int64, [_vp]),
     "nmf_frame_iters": (ctypes.c_int64, [_vp, _vp, _i64]),
+    "nmf_frame_visits": (ctypes.c_int64, [_vp, _vp, _i64]),
     "nmf_subtract": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp]),
     "nmf_warmstart_param_count": (ctypes.c_int64, [_i32]),
     "nmf_warmstart_init": (ctypes.c_int, [_vp, _vp, _i32, _u64, _vp]),
@@ -448,6 +449,19 @@ def frame_iters(handle=None, device=0):
         return None
     buf = np.zeros(n, np.int32)
     _check(int(lib().nmf_frame_iters(h.h, buf.ctypes.data, n)))
+    return buf
+
+
+def frame_visits(handle=None, device=0):
+    """How many times the last masked-Gram projection on the handle took each
+    frame from its queue (int32 numpy array; None if none ran)."""
+    import numpy as np
+    h = handle or default_handle(device)
+    n = _check(int(lib().nmf_frame_visits(h.h, None, 0)))
+    if n == 0:
+        return None
+    buf = np.zeros(n, np.int32)
+    _check(int(lib().nmf_frame_visits(h.h, buf.ctypes.data, n)))
     return buf
 
 

@@ -19,7 +19,7 @@ EXPECTED = {
     "nmf_device_clock_khz", "nmf_warmstart_param_count", "nmf_warmstart_init",
     "nmf_warmstart_pool", "nmf_warmstart_step", "nmf_warmstart_train", "nmf_warmstart_infer",
     "nmf_autotune_report", "nmf_closest_frames", "nmf_best_factor", "nmf_build_basis_sequential",
-    "nmf_warm_fallbacks", "nmf_frame_iters",
+    "nmf_warm_fallbacks", "nmf_frame_iters", "nmf_frame_visits",
 }
 
 
@@ -132,6 +132,7 @@ def test_project_and_subtract_validation(L):
     assert L.nmf_project(None, FAKE, 4, 100, FAKE + 4, FAKE + 8, 3, ctypes.byref(tp), None,
                          FAKE + 12, None, None, None) == nmf.NMF_ERR_UNSUPPORTED
     assert L.nmf_frame_iters(None, None, 0) == nmf.NMF_ERR_ARG
+    assert L.nmf_frame_visits(None, None, 0) == nmf.NMF_ERR_ARG
     assert L.nmf_subtract(None, FAKE, FAKE + 4, FAKE + 8, FAKE + 12, 2, 4, 100, None, None, None,
                           None) == nmf.NMF_ERR_ARG
     assert L.nmf_subtract(None, FAKE, FAKE + 4, FAKE + 8, FAKE + 12, 2, 0, 100, None, None,

@@ -260,6 +260,31 @@ def test_ragged_many_frames_longest_first_order_is_a_permutation():
     assert np.max(np.abs(Cg - Co) / scale) < 1e-4
     t = host(ticks).astype(np.int64).reshape(f, 2)
     assert np.all(t[:, 0] > 0) and np.all(t[:, 1] >= t[:, 0])
+    # the queue handed out every frame exactly once
+    v = nmf.frame_visits()
+    assert v is not None and v.shape == (f,) and np.all(v == 1)
+
+
+@pytest.mark.parametrize("k,f", [(60, 700), (100, 1500), (200, 300)])
+def test_queue_visits_each_frame_once(k, f):
+    """Dense frames (one or two-phase launch by K) and CSR frames: the
+    persistent launch takes every frame from its queue exactly once, also on
+    a graph replay of the same call."""
+    p = 900
+    H = _basis(k, p, seed=k)
+    T, MT = _photon_frames(H, f, seed=k + 1)
+    for rep in range(2):
+        say("queue visits dense", k, f, rep)
+        nmf.project(dev(H), dev(T), dev(MT), 5, seed=1, gram=True)
+        v = nmf.frame_visits()
+        assert v.shape == (f,) and np.all(v == 1)
+    g = np.random.default_rng(k)
+    sizes = g.integers(0, p + 1, f)
+    offs, pix, val, wt = _ragged(H, sizes, seed=k + 2, binary=True)
+    say("queue visits ragged", k, f)
+    nmf.project_ragged(dev(H), dev_i64(offs), dev_i32(pix), dev(val), None, 5, seed=1)
+    v = nmf.frame_visits()
+    assert v.shape == (f,) and np.all(v == 1)
 
 
 def _check_ratio(T, MT, H, C0, t, ce):
