@@ -85,6 +85,12 @@ __host__ __device__ constexpr int wide_stage_bytes() {
 __device__ __forceinline__ void dma16(const void* src, unsigned char* lds) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
 }
+// The same for data read once per launch: streamed (non-temporal), so it
+// does not displace the operand sets every workgroup re-reads from L2.
+__device__ __forceinline__ void dma16_stream(const void* src, unsigned char* lds) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0,
+                                   2 /* nt */);
+}
 // The same with 4 bytes per lane: lane i's bytes land at lds + 4 i.
 __device__ __forceinline__ void dma4(const void* src, unsigned char* lds) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
@@ -222,11 +228,11 @@ __global__ __launch_bounds__(64 * WIDE_NW, 1) void k_wide(DualArgs a) {
   auto fetch_data = [&](int tr, int buf) {
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      dma16(dcol + (int64_t)tr * 4096 + (lofs + u * 1024), dslot + buf * 4096 + u * 1024);
+      dma16_stream(dcol + (int64_t)tr * 4096 + (lofs + u * 1024), dslot + buf * 4096 + u * 1024);
     if constexpr (MWD) {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        dma16(mcol + (int64_t)tr * 4096 + (lofs + u * 1024), mslot + buf * 4096 + u * 1024);
+        dma16_stream(mcol + (int64_t)tr * 4096 + (lofs + u * 1024), mslot + buf * 4096 + u * 1024);
     }
   };
   // weights through registers (when their LDS slots do not fit)
@@ -686,7 +692,8 @@ __global__ __launch_bounds__(64 * WIDE_NW, 1) void k_wide(DualArgs a) {
             dma16(osrc + (lofs + LS * 16 * piece), odst + LS * 16 * piece);
           } else if (piece < PT + 4) {
             const int u = piece - PT;
-            dma16(dcol + (int64_t)n2 * 4096 + (lofs + u * 1024), dslot + buf2 * 4096 + u * 1024);
+            dma16_stream(dcol + (int64_t)n2 * 4096 + (lofs + u * 1024),
+                         dslot + buf2 * 4096 + u * 1024);
           } else if (piece == PT + 4) {
             fetch_bits(n2, buf2);
           }
