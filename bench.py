@@ -453,7 +453,12 @@ def tolerance_leg(args, nmf, synth, h, torch):
     (Ctr, _), t_tgt = timed(lambda: nmf.project(Hd, Ttr, Mtr, ITERS, gram=True, precision="fp32",
                                                 seed=9, tol=1e-8, check_every=CE, handle=h))
     Xtr, str_ = nmf.ws_pool(Ttr, Mtr, ps.ny, ps.nx, handle=h)
-    Gm = torch.from_numpy((H64 @ H64.T).astype(np.float32)).to(dev)
+    # training metric G = I: the loss measures coefficient error.  With the
+    # model-space metric (G = H H^T) the network reaches a 2% model error on
+    # these strongly correlated components but leaves ~30% of each frame's
+    # support coefficients near zero, which multiplicative updates are slow
+    # to grow back
+    Gm = torch.eye(K, dtype=torch.float32, device=dev)
     st = nmf.ws_init(K, seed=11, handle=h)
     EPOCHS = 40
     hist, t_train = timed(lambda: nmf.ws_train(st, Xtr, str_, Ctr, Gm, K, epochs=EPOCHS, batch=64,
@@ -468,13 +473,20 @@ def tolerance_leg(args, nmf, synth, h, torch):
 
     C0 = infer()
     warm_err0 = errors(C0)
+    c0 = C0[:n_s].detach().cpu().double().numpy()
+    sup = fx["w_star"] > 1e-2 * fx["w_star"].mean(axis=1, keepdims=True)
+    ratio = c0[sup] / fx["w_star"][sup]
     warm = scan("batched warm", pre=infer)
     warm["form"] = ("masked-Gram, one persistent launch, FP32 Gram products, warm start from "
                     "the network (pooling and inference inside the timed region), per-frame "
                     "stop rule, cold restart of a frame that misses it by the cap")
     warm["network_start_median_error"] = float(np.median(warm_err0))
+    warm["network_start_coefficients"] = {
+        "median_relative_error_on_support": float(np.median(np.abs(ratio - 1.0))),
+        "fraction_of_support_below_a_tenth": float(np.mean(ratio < 0.1))}
     warm["training"] = {"frames": args.train_frames, "targets": "the library's masked-Gram "
-                        "projection to tol 1e-8", "epochs": EPOCHS, "batch": 64, "lr": 1e-3,
+                        "projection to tol 1e-8", "loss": "relative coefficient error (metric G = I)",
+                        "epochs": EPOCHS, "batch": 64, "lr": 1e-3,
                         "loss_first_last": [float(hist[0]), float(hist[-1])],
                         "seconds_targets": t_tgt, "seconds_training": t_train}
     return {
