@@ -14,7 +14,9 @@ import threading
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libnmf_mi355x.so")
+# NMF_LIB names another build of the same library (the host-sanitizer build
+# the CPU tests make); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("NMF_LIB") or os.path.join(_PKG, "libnmf_mi355x.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "nmf_mi355x.h")
 
 NMF_OK = 0
