@@ -563,11 +563,12 @@ hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, h
 // give the same bits; they differ only in how many frames a compute unit
 // iterates at once (several small workgroups instead of one large one).
 // ---------------------------------------------------------------------------
-template <int KP>
+template <int KP, int KR>
 __global__ __launch_bounds__(KP <= 64 ? 64 : 128) void k_gram_iter(GramArgs a) {
+  static_assert(KR % 8 == 0 && KR <= KP, "row length: K rounded up to 8");
   constexpr int NT = KP <= 64 ? 64 : 128;
   constexpr int NW = NT / 64;
-  constexpr int KQ = KP / 4;
+  constexpr int KQ = KR / 4;  // the products with the zero padding of G are left out
   __shared__ __align__(16) float cb[2][KP];
   __shared__ __align__(16) float dsh[KP];
   __shared__ double wsel[2][NW];
@@ -576,10 +577,10 @@ __global__ __launch_bounds__(KP <= 64 ? 64 : 128) void k_gram_iter(GramArgs a) {
   const int K = a.K;
   const int j = threadIdx.x, wave = j >> 6, lane = j & 63;
   const uint64_t key = sm_key(a.seed, 2);
-  float g[KP];
+  float g[KR];
   const float* Gr = a.Gf + (int64_t)f * K * K + (j < K ? j : 0) * K;
 #pragma unroll
-  for (int i = 0; i < KP; ++i) g[i] = (j < K && i < K) ? Gr[i] : 0.f;
+  for (int i = 0; i < KR; ++i) g[i] = (j < K && i < K) ? Gr[i] : 0.f;
   const double bj = j < KP ? a.bf[(int64_t)f * KP + j] : 0.0;
   const bool warm_kept = a.warm && a.fallback && a.fallback[f] == 0;
   const int ce = a.check_every;
@@ -673,16 +674,36 @@ __global__ __launch_bounds__(KP <= 64 ? 64 : 128) void k_gram_iter(GramArgs a) {
   if (a.ticks && j == 0) a.ticks[2 * (int64_t)f + 1] = wall_clock64();
 }
 
-hipError_t launch_gram_iter(int kp, const GramArgs& a, hipStream_t s) {
-  if (a.F <= 0) return hipSuccess;
-  switch (kp) {
-    case 32: hipLaunchKernelGGL(k_gram_iter<32>, dim3(a.F), dim3(64), 0, s, a); break;
-    case 64: hipLaunchKernelGGL(k_gram_iter<64>, dim3(a.F), dim3(64), 0, s, a); break;
-    case 96: hipLaunchKernelGGL(k_gram_iter<96>, dim3(a.F), dim3(128), 0, s, a); break;
-    case 128: hipLaunchKernelGGL(k_gram_iter<128>, dim3(a.F), dim3(128), 0, s, a); break;
+template <int KP, int KR>
+static void gram_iter_go(const GramArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_gram_iter<KP, KR>), dim3(a.F), dim3(KP <= 64 ? 64 : 128), 0, s, a);
+}
+
+// The products of a row with G run over K rounded up to 8 (the rest of a
+// KP-long row is zero padding), so the kernel comes in one form per K / 8.
+template <int KP>
+static hipError_t gram_iter_kp(int K, const GramArgs& a, hipStream_t s) {
+  const int r = (K + 7) / 8 * 8;
+  switch (KP - r) {
+    case 0: gram_iter_go<KP, KP>(a, s); break;
+    case 8: gram_iter_go<KP, KP - 8>(a, s); break;
+    case 16: gram_iter_go<KP, KP - 16>(a, s); break;
+    case 24: gram_iter_go<KP, KP - 24>(a, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_gram_iter(int kp, const GramArgs& a, hipStream_t s) {
+  if (a.F <= 0) return hipSuccess;
+  if (a.K < 1 || a.K > kp || kp - a.K >= 32) return hipErrorInvalidValue;
+  switch (kp) {
+    case 32: return gram_iter_kp<32>(a.K, a, s);
+    case 64: return gram_iter_kp<64>(a.K, a, s);
+    case 96: return gram_iter_kp<96>(a.K, a, s);
+    case 128: return gram_iter_kp<128>(a.K, a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // ---------------------------------------------------------------------------
