@@ -103,3 +103,35 @@ def test_miri_fullsize_500_iterations(precision):
     z = _fixture("miri")
     lib = synth.make_cfg3(frames=1)
     _run(lib, z, precision, nmf.F_BINARY_WEIGHTS)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_projection_set_to_tolerance_against_exact_nnls(precision):
+    """Full-size projection to the stop rule: 1024 STIS-shaped frames (200x200
+    px) on the seeded K = 100 basis in one masked-Gram call (two-launch form),
+    judged on the 256 frames whose exact weighted NNLS solutions the oracle
+    stored.  With stop threshold 2e-7 every judged frame is within 1e-4 of
+    its exact NNLS model (||m o (c H - w* H)|| / ||m o w* H||) in both
+    precision forms of the Gram products (measured max 9.8e-5 in both: the
+    stop rule, not the ~1e-6 relative error split-precision products put
+    into G, sets how close a frame gets)."""
+    import hashlib
+    z = np.load(os.path.join(GOLDEN, "oracle_nnls_proj_k100.npz"))
+    n_s = int(z["n_sample"])
+    ps = synth.make_projection_set(int(z["n_frames"]))
+    sha = lambda x: hashlib.sha256(np.ascontiguousarray(x, np.float32).tobytes()).hexdigest()
+    assert sha(ps.H) == str(z["h_sha"]) and sha(ps.T[:n_s]) == str(z["t_sha"])
+    say("projection set to tolerance", precision)
+    C, rep = nmf.project(dev(ps.H), dev(ps.T), dev(ps.MT), 400000, gram=True,
+                         precision=precision, seed=7, tol=2e-7, check_every=500)
+    its = nmf.frame_iters()
+    assert np.all(nmf.frame_visits() == 1)
+    H = ps.H.astype(np.float64)
+    ref = z["w_star"] @ H
+    Ms = ps.MT[:n_s].astype(np.float64)
+    err = (np.linalg.norm(Ms * (host(C)[:n_s] @ H - ref), axis=1)
+           / np.linalg.norm(Ms * ref, axis=1))
+    print(f"  model error vs exact NNLS: median {np.median(err):.2e} max {err.max():.2e}; "
+          f"iterations mean {its.mean():.0f} max {its.max()}", flush=True)
+    assert np.all(its < 400000) and np.all(its % 500 == 0)
+    assert err.max() <= 1e-4
