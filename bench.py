@@ -417,7 +417,7 @@ def tolerance_leg(args, nmf, synth, h, torch):
             c0 = C0
             if pre is not None:
                 c0 = pre()
-            return nmf.project(Hd, Td, Md, ITERS, gram=True, precision="fp32", seed=7,
+            return nmf.project(Hd, Td, Md, ITERS, gram=True, precision="bf16x3", seed=7,
                                C_init=c0, warm=c0 is not None, tol=tau, check_every=CE, handle=h)
         (C, rep), dt = timed(go)
         its = nmf.frame_iters(h)
@@ -439,10 +439,10 @@ def tolerance_leg(args, nmf, synth, h, torch):
                 break
         return r
 
-    nmf.project(Hd, Td, Md, 10, gram=True, precision="fp32", seed=7, tol=1e-5, check_every=5,
+    nmf.project(Hd, Td, Md, 10, gram=True, precision="bf16x3", seed=7, tol=1e-5, check_every=5,
                 handle=h)  # warm-up
     cold = scan("batched cold")
-    cold["form"] = ("masked-Gram, one persistent launch, FP32 Gram products, cold start, "
+    cold["form"] = ("masked-Gram, one persistent launch, bf16x3 Gram products, cold start, "
                     "per-frame stop rule (model change over check_every iterations)")
 
     # warm start: the method projects a training set to stationarity, the
@@ -477,7 +477,7 @@ def tolerance_leg(args, nmf, synth, h, torch):
     sup = fx["w_star"] > 1e-2 * fx["w_star"].mean(axis=1, keepdims=True)
     ratio = c0[sup] / fx["w_star"][sup]
     warm = scan("batched warm", pre=infer)
-    warm["form"] = ("masked-Gram, one persistent launch, FP32 Gram products, warm start from "
+    warm["form"] = ("masked-Gram, one persistent launch, bf16x3 Gram products, warm start from "
                     "the network (pooling and inference inside the timed region), per-frame "
                     "stop rule, cold restart of a frame that misses it by the cap")
     warm["network_start_median_error"] = float(np.median(warm_err0))
