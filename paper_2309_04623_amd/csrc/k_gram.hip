@@ -27,6 +27,11 @@
 
 namespace nmf {
 
+// One LDS DMA of 16 bytes per lane: lane i's bytes land at lds + 16 i.
+__device__ __forceinline__ void gram_dma16(const void* src, float* lds) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+
 template <int KP>
 __host__ __device__ constexpr int gram_tiles() {
   return (KP / 32) * (KP / 32 + 1) / 2;
@@ -53,7 +58,7 @@ constexpr int GT_STRIDE = 20;
 
 template <int KP>
 __host__ __device__ constexpr int gram_stage_floats(int prec) {
-  return 32 * KP + 64 + (prec == PREC_BF16X3 ? 4 * KP * GT_STRIDE : 0);
+  return 64 * KP + 288 + (prec == PREC_BF16X3 ? 4 * KP * GT_STRIDE : 0);
 }
 
 template <int KP, bool RAGGED, int PREC, bool FORM>
@@ -70,11 +75,14 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   constexpr int KQ = KP / 4;
   constexpr int FOLD = 8;  // chunks summed in FP32 before folding into FP64
   const int K = a.K;
-  float* Hs = lds;            // [32][KP] gathered H^T rows
-  float* ms = lds + 32 * KP;  // [32] weights
-  float* ts = ms + 32;        // [32] data
+  // [2][32][KP] gathered H^T rows (the chunk in use and the next one)
+  float* Hsb = lds;
+  // rings of three chunks' pixel indices, weights and data ([3][32] each)
+  int* pixr = reinterpret_cast<int*>(lds + 64 * KP);
+  float* msr = lds + 64 * KP + 96;
+  float* tsr = msr + 96;
   // bf16 hi/lo of H^T and (H o m)^T, [KP][GT_STRIDE] dwords (2 pixels each)
-  uint32_t* hT_hi = reinterpret_cast<uint32_t*>(lds + 32 * KP + 64);
+  uint32_t* hT_hi = reinterpret_cast<uint32_t*>(lds + 64 * KP + 288);
   uint32_t* hT_lo = hT_hi + KP * GT_STRIDE;
   uint32_t* hmT_hi = hT_lo + KP * GT_STRIDE;
   uint32_t* hmT_lo = hmT_hi + KP * GT_STRIDE;
@@ -96,7 +104,6 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       tmj[q] = -1;
     }
   }
-  f32x4* Hs4 = reinterpret_cast<f32x4*>(Hs);
   const uint64_t key = sm_key(a.seed, 2);
   int bad = 0;
 
@@ -142,65 +149,96 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
     double bacc = 0.0;
     int nfold = 0;
 
-    for (int64_t base = s; base < e; base += 32) {
-      // ---- stage 32 pixels: rows of H^T, weights, data -------------------
-      for (int x = tid; x < 32 * KQ; x += NTH) {
-        const int jr = x / KQ, kq = x - jr * KQ;
-        const int64_t jj = base + jr;
-        f32x4 v = {0.f, 0.f, 0.f, 0.f};
-        if (jj < e) {
-          int prow;
-          if constexpr (RAGGED) {
-            prow = a.pix[jj];
-            if (prow < 0 || prow >= a.P) prow = -1;
-          } else {
-            prow = (int)jj;
-          }
-          if (prow >= 0) v = *reinterpret_cast<const f32x4*>(a.HT + lop_f32(prow, 4 * kq, KP));
+    // Pixel chunks of 32 in a software pipeline: the rows of H^T of chunk
+    // c + 1 are gathered by LDS DMA (one 16-byte piece per lane, no
+    // registers) while chunk c is reduced, and the pixel indices, weights and
+    // data of chunk c + 2 are loaded then; each chunk ends with one barrier,
+    // which also retires its DMAs.  A pixel outside the frame or with an
+    // invalid index gathers row 0 (finite) under weight 0, so it adds
+    // exactly nothing.
+    int mp = 0;
+    float mm = 0.f, mt = 0.f;
+    auto meta_load = [&](int64_t b0) {  // threads < 32: chunk at b0
+      const int64_t jj = b0 + tid;
+      mp = -1;
+      mm = 0.f;
+      mt = 0.f;
+      if (jj < e) {
+        if constexpr (RAGGED) {
+          mp = a.pix[jj];
+          mm = a.wt ? a.wt[jj] : 1.0f;
+          mt = a.val[jj];
+        } else {
+          mp = (int)jj;
+          mm = a.MT[(int64_t)f * a.P + jj];
+          mt = a.T[(int64_t)f * a.P + jj];
         }
-        Hs4[x] = v;
       }
-      if (tid < 32) {
-        const int64_t jj = base + tid;
-        float m = 0.f, t = 0.f;
-        if (jj < e) {
-          if constexpr (RAGGED) {
-            const int prow = a.pix[jj];
-            m = a.wt ? a.wt[jj] : 1.0f;
-            t = a.val[jj];
-            if (prow < 0 || prow >= a.P) {
-              bad |= 16;
-              m = 0.f;
-            }
-          } else {
-            m = a.MT[(int64_t)f * a.P + jj];
-            t = a.T[(int64_t)f * a.P + jj];
-          }
-          if (!(m >= 0.f) || isinf(m)) {
-            bad |= 4;
-            m = 0.f;
-          }
-          if (a.binary) m = m > 0.f ? 1.f : 0.f;
-          if (m > 0.f) {
-            if (!isfinite(t)) {
-              bad |= 1;
-              t = 0.f;
-            } else if (t < 0.f) {
-              if (a.clip_negative) {
-                m = 0.f;
-                t = 0.f;
-              } else {
-                bad |= 2;
-              }
-            }
-          } else {
-            t = 0.f;
-          }
+    };
+    auto meta_store = [&](int slot, int64_t b0) {  // threads < 32: validated
+      const int64_t jj = b0 + tid;
+      float m = 0.f, t = 0.f;
+      int prow = 0;
+      if (jj < e) {
+        m = mm;
+        t = mt;
+        prow = mp;
+        if (RAGGED && (prow < 0 || prow >= a.P)) {
+          bad |= 16;
+          m = 0.f;
+          prow = 0;
         }
-        ms[tid] = m;
-        ts[tid] = t;
+        if (!(m >= 0.f) || isinf(m)) {
+          bad |= 4;
+          m = 0.f;
+        }
+        if (a.binary) m = m > 0.f ? 1.f : 0.f;
+        if (m > 0.f) {
+          if (!isfinite(t)) {
+            bad |= 1;
+            t = 0.f;
+          } else if (t < 0.f) {
+            if (a.clip_negative) {
+              m = 0.f;
+              t = 0.f;
+            } else {
+              bad |= 2;
+            }
+          }
+        } else {
+          t = 0.f;
+        }
+      }
+      pixr[32 * slot + tid] = prow;
+      msr[32 * slot + tid] = m;
+      tsr[32 * slot + tid] = t;
+    };
+    auto gather = [&](int slot, float* dst) {  // all waves: 32 rows of H^T
+#pragma unroll
+      for (int i = wave; i < KQ / 2; i += NWV) {
+        const int x = 64 * i + lane, jr = x / KQ, kq = x - jr * KQ;
+        gram_dma16(a.HT + lop_f32(pixr[32 * slot + jr], 4 * kq, KP), dst + 256 * i);
+      }
+    };
+    if (s < e) {
+      if (tid < 32) {
+        meta_load(s);
+        meta_store(0, s);
+        meta_load(s + 32);
+        meta_store(1, s + 32);
       }
       __syncthreads();
+      gather(0, Hsb);
+      __syncthreads();
+    }
+    int c = 0;
+    for (int64_t base = s; base < e; base += 32, ++c) {
+      const int sl = c % 3;
+      float* Hs = Hsb + (c & 1) * 32 * KP;
+      const float* ms = msr + 32 * sl;
+      const float* ts = tsr + 32 * sl;
+      if (base + 32 < e) gather((c + 1) % 3, Hsb + ((c + 1) & 1) * 32 * KP);
+      if (tid < 32) meta_load(base + 64);
       if constexpr (PREC == PREC_BF16X3) {
         // transposed split staging: thread -> (component, pixel pair); the
         // reads of Hs are consecutive across threads, the dword writes land
@@ -262,6 +300,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
         nfold = 0;
         fold();
       }
+      if (tid < 32) meta_store((c + 2) % 3, base + 64);
       __syncthreads();
     }
     fold();
@@ -491,7 +530,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
 }
 
 size_t gram_lds_bytes(int K, int KP, int prec) {
-  const int stage = 32 * KP + 64 + (prec == PREC_BF16X3 ? 4 * KP * GT_STRIDE : 0);
+  const int stage = 64 * KP + 288 + (prec == PREC_BF16X3 ? 4 * KP * GT_STRIDE : 0);
   const int goff = (std::max(K * K, stage) + 3) & ~3;
   return (size_t)goff * 4 + (size_t)KP * 8 + (size_t)KP * 4 * 2;  // G | b | c, d
 }
