@@ -7,10 +7,13 @@
 // frames from a device queue; per frame it
 //   1. streams the frame's pixels in chunks of 32, staging the gathered rows
 //      of H^T (K values per pixel), m and t in LDS, and accumulates the
-//      upper-triangle 32x32 tiles of G on MFMA (tiles spread over the four
-//      waves) and b on the vector units (FP64 accumulation);
-//   2. writes G to LDS, gives thread j row j of G in registers, and runs all
-//      iterations c_j <- max(c_j b_j / (c G)_j, eps) with c in LDS.
+//      upper-triangle 32x32 tiles of G on MFMA (tiles spread over the
+//      waves) and b on the vector units (FP64 sums, each component's pixels
+//      split over the groups of threads that fit the workgroup);
+//   2. for K <= 128 hands G, b and the start to k_gram_iter (below), which
+//      iterates several frames per compute unit with a row of G per lane;
+//      for larger K writes G to LDS and runs all iterations
+//      c_j <- max(c_j b_j / (c G)_j, eps) itself, with c in LDS.
 // Pixels appear only through the staged chunks, so dense frames (all
 // pixels, weight row of M_T) and CSR frames share the kernel.
 //
@@ -64,6 +67,7 @@ __host__ __device__ constexpr int gram_stage_floats(int prec) {
 template <int KP, bool RAGGED, int PREC, bool FORM>
 __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   static_assert(!FORM || KP <= 128, "the two-phase form keeps a row of G per lane");
+  static_assert(FORM || KP > 128, "K <= 128 iterates in k_gram_iter");
   extern __shared__ __align__(16) float lds[];
   __shared__ int qslot;
   __shared__ double wsel[2][gram_waves<KP>()];
@@ -74,6 +78,9 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   constexpr int TPW = (NT + NWV - 1) / NWV;
   constexpr int KQ = KP / 4;
   constexpr int FOLD = 8;  // chunks summed in FP32 before folding into FP64
+  // b = H (m o t): BG groups of KP threads, each group BPX pixels of a chunk
+  constexpr int BG = NTH / KP >= 8 ? 8 : NTH / KP >= 4 ? 4 : NTH / KP >= 2 ? 2 : 1;
+  constexpr int BPX = 32 / BG;
   const int K = a.K;
   // [2][32][KP] gathered H^T rows (the chunk in use and the next one)
   float* Hsb = lds;
@@ -93,6 +100,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int col = lane & 31, half = lane >> 5;
+  const int bgrp = tid / KP, bcomp = tid - bgrp * KP;
   int tmi[TPW], tmj[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
@@ -289,10 +297,13 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
           }
         }
       }
-      // ---- b += H (m o t) --------------------------------------------------
-      if (tid < KP) {
-#pragma unroll 8
-        for (int jr = 0; jr < 32; ++jr) bacc += (double)(Hs[jr * KP + tid] * ms[jr]) * (double)ts[jr];
+      // ---- b += H (m o t): thread (bgrp, bcomp) sums pixels bgrp*BPX.. ----
+      if (bgrp < BG) {
+#pragma unroll
+        for (int u = 0; u < BPX; ++u) {
+          const int jr = bgrp * BPX + u;
+          bacc += (double)(Hs[jr * KP + bcomp] * ms[jr]) * (double)ts[jr];
+        }
       }
       // Two-level sum: FOLD chunks in the FP32 MFMA accumulators, then into
       // FP64 totals (G entries are sums of up to P_f / 2 positive terms).
@@ -304,6 +315,13 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       __syncthreads();
     }
     fold();
+    // b: the groups' partial sums in group order (bsh is not aliased by the
+    // staging area, so this needs no barrier before it)
+#pragma unroll
+    for (int gi = 0; gi < BG; ++gi) {
+      if (bgrp == gi) bsh[bcomp] = bcomp < K ? (gi == 0 ? bacc : bsh[bcomp] + bacc) : 0.0;
+      if (BG > 1) __syncthreads();
+    }
 
     // ---- G to LDS (both triangles), b and the starting coefficients -------
 #pragma unroll
@@ -322,7 +340,6 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       }
     }
     if (tid < KP) {
-      bsh[tid] = tid < K ? bacc : 0.0;
       float c0 = 0.f;
       if (tid < K) {
         c0 = a.C_init ? a.C_init[(int64_t)f * K + tid] : sm_uniform(key, (uint64_t)f * K + tid);
@@ -383,107 +400,98 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       continue;
     }
 
-    // ---- iterations: (c G)_j with row j of G in registers (K <= 128) or
-    // read from LDS (consecutive j across lanes, conflict-free) ------------
-    // Optional per-frame stop rule: every check_every iterations the model
-    // change since the previous check, d = c - c_prev, is tested against
-    // the model, d G d^T <= tol^2 c G c^T (both in FP64; c G is the
-    // denominator just formed, d G one more product).  A warm-started frame
-    // that has not met the rule by the cap restarts from the cold start.
-    const int j = tid;
-    const double bj = j < KP ? bsh[j] : 0.0;
-    const f32x4* c4 = reinterpret_cast<const f32x4*>(csh);
-    float* dsh = csh + KP;
-    const f32x4* d4 = reinterpret_cast<const f32x4*>(dsh);
-    const int ce = a.check_every;
-    __shared__ int run_sh[2];  // iterations run, rule met
-    float g[(KP <= 128 && !FORM) ? KP : 1];
-    if constexpr (KP <= 128 && !FORM) {
+    if constexpr (!FORM) {
+      // ---- iterations (K > 128): (c G)_j with G read from LDS -------------
+      // Two threads, j and j + 256, share row j of the product: each sums half
+      // of the components (consecutive j across lanes read consecutive words,
+      // conflict-free), the upper one leaves its sum in LDS for the lower one,
+      // which owns coefficient j.  Optional per-frame stop rule: every
+      // check_every iterations the model change since the previous check,
+      // d = c - c_prev, is tested against the model, d G d^T <= tol^2 c G c^T
+      // (both in FP64; c G is the denominator just formed, d G one more
+      // product).  A warm-started frame that has not met the rule by the cap
+      // restarts from the cold start.
+      static_assert(NTH == 512 && KP <= 256, "two threads per row of G");
+      const int j = tid & 255, hf = tid >> 8;
+      const bool own = hf == 0 && j < K;  // thread owns coefficient j
+      const double bj = own ? bsh[j] : 0.0;
+      float* psh = reinterpret_cast<float*>(bsh);  // upper half's sums (b is in bj now)
+      const f32x4* c4 = reinterpret_cast<const f32x4*>(csh);
+      float* dsh = csh + KP;
+      const f32x4* d4 = reinterpret_cast<const f32x4*>(dsh);
+      const int ce = a.check_every;
+      __shared__ int run_sh[2];  // iterations run, rule met
+      const float* gcol = G + (j < K ? j : 0);
+      // quads of components: the lower half takes [0, h4), the upper [h4, K/4)
+      // and the last K % 4; each index i goes into partial sum i % 4
+      const int K4 = K >> 2, kr = K & 3, h4 = (K4 + 1) >> 1;
+      const int qa = hf ? h4 : 0, qb = hf ? K4 : h4;
+      auto matvec_part = [&](const float* v, const f32x4* v4) -> float {
+        float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+        if (j < K) {
+          int i4 = qa;
+          // eight column entries per step, all read before they are used
+          for (; i4 + 2 <= qb; i4 += 2) {
+            const f32x4 ca = v4[i4], cb = v4[i4 + 1];
+            const float* gc = gcol + 4 * i4 * K;
+            float gv[8];
 #pragma unroll
-      for (int i = 0; i < KP; ++i) g[i] = (j < K && i < K) ? G[j * K + i] : 0.f;
-    }
-    const float* gcol = G + (j < K ? j : 0);
-    // (v G)_j for a vector v in LDS
-    auto matvec = [&](const float* v, const f32x4* v4) -> float {
-      float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
-      if constexpr (KP <= 128 && !FORM) {
-#pragma unroll
-        for (int i4 = 0; i4 < KQ; ++i4) {
-          const f32x4 cv = v4[i4];
-          d0 = fmaf(cv[0], g[4 * i4 + 0], d0);
-          d1 = fmaf(cv[1], g[4 * i4 + 1], d1);
-          d2 = fmaf(cv[2], g[4 * i4 + 2], d2);
-          d3 = fmaf(cv[3], g[4 * i4 + 3], d3);
-        }
-      } else if (j < K) {
-        for (int i = 0; i < K; ++i) d0 = fmaf(v[i], gcol[i * K], d0);
-      }
-      return (d0 + d1) + (d2 + d3);
-    };
-    int its_total = 0;
-    bool met = false;
-    for (int pass = 0; pass < 2; ++pass) {
-      if (pass == 1) {
-        // the warm start missed the rule by the cap: cold start, same cap
-        if (!(warm_kept && ce > 0 && !met)) break;
-        if (tid < KP) csh[tid] = tid < K ? sm_uniform(key, (uint64_t)f * K + tid) : 0.f;
-        if (a.fallback && tid == 0) a.fallback[f] = 2;
-        __syncthreads();
-      }
-      if constexpr (KP <= 64) {
-        // One wave iterates: lane j keeps row j of G in registers and the
-        // coefficients travel through LDS.  A wave's LDS accesses execute in
-        // program order, so each iteration's broadcast reads see the previous
-        // iteration's writes without a workgroup barrier; the other waves
-        // wait at the barrier below.
-        if (wave == 0) {
-          float cj = j < KP ? csh[j] : 0.f, cp = cj;
-          int it = 0;
-          bool stop = false;
-          for (; it < a.iters; ++it) {
-            const float den = matvec(csh, c4);
-            if (ce > 0 && it > 0 && it % ce == 0) {
-              const float dj = j < K ? cj - cp : 0.f;
-              if (j < KP) dsh[j] = dj;
-              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-              __builtin_amdgcn_wave_barrier();
-              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-              const float dg = matvec(dsh, d4);
-              const double q1 = wave_sum(j < K ? (double)dj * (double)dg : 0.0);
-              const double q2 = wave_sum(j < K ? (double)cj * (double)den : 0.0);
-              if (q1 <= a.tol2 * q2) {
-                stop = true;
-                break;
-              }
-              cp = cj;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            if (j < K) {
-              cj = mu_apply_d(cj, bj, (double)den, a.eps);
-              csh[j] = cj;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+            for (int u = 0; u < 8; ++u) gv[u] = gc[u * K];
+            d0 = fmaf(ca[0], gv[0], d0);
+            d1 = fmaf(ca[1], gv[1], d1);
+            d2 = fmaf(ca[2], gv[2], d2);
+            d3 = fmaf(ca[3], gv[3], d3);
+            d0 = fmaf(cb[0], gv[4], d0);
+            d1 = fmaf(cb[1], gv[5], d1);
+            d2 = fmaf(cb[2], gv[6], d2);
+            d3 = fmaf(cb[3], gv[7], d3);
           }
-          if (lane == 0) {
-            run_sh[0] = it;
-            run_sh[1] = stop ? 1 : 0;
+          if (i4 < qb) {
+            const f32x4 cv = v4[i4];
+            const float* gc = gcol + 4 * i4 * K;
+            d0 = fmaf(cv[0], gc[0], d0);
+            d1 = fmaf(cv[1], gc[K], d1);
+            d2 = fmaf(cv[2], gc[2 * K], d2);
+            d3 = fmaf(cv[3], gc[3 * K], d3);
+          }
+          if (hf) {
+            const float* gc = gcol + 4 * K4 * K;
+            if (kr > 0) d0 = fmaf(v[4 * K4], gc[0], d0);
+            if (kr > 1) d1 = fmaf(v[4 * K4 + 1], gc[K], d1);
+            if (kr > 2) d2 = fmaf(v[4 * K4 + 2], gc[2 * K], d2);
           }
         }
-      } else {
-        float cj = j < K ? csh[j] : 0.f, cp = cj;
+        return (d0 + d1) + (d2 + d3);
+      };
+      __syncthreads();  // every bj is read before psh (over b) is written
+      int its_total = 0;
+      bool met = false;
+      for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+          // the warm start missed the rule by the cap: cold start, same cap
+          if (!(warm_kept && ce > 0 && !met)) break;
+          if (tid < KP) csh[tid] = tid < K ? sm_uniform(key, (uint64_t)f * K + tid) : 0.f;
+          if (a.fallback && tid == 0) a.fallback[f] = 2;
+          __syncthreads();
+        }
+        float cj = own ? csh[j] : 0.f, cp = cj;
         int it = 0;
         bool stop = false;
         for (; it < a.iters; ++it) {
-          const float den = matvec(csh, c4);
+          float den = matvec_part(csh, c4);
+          if (hf == 1 && j < K) psh[j] = den;
+          __syncthreads();
+          if (own) den += psh[j];
           if (ce > 0 && it > 0 && it % ce == 0) {
-            const float dj = j < K ? cj - cp : 0.f;
-            if (j < KP) dsh[j] = dj;
+            const float dj = own ? cj - cp : 0.f;
+            if (hf == 0 && j < KP) dsh[j] = dj;
             __syncthreads();
-            const float dg = matvec(dsh, d4);
-            const double q1 = wave_sum(j < K ? (double)dj * (double)dg : 0.0);
-            const double q2 = wave_sum(j < K ? (double)cj * (double)den : 0.0);
+            float dg = matvec_part(dsh, d4);
+            if (hf == 1 && j < K) psh[j] = dg;
+            __syncthreads();
+            if (own) dg += psh[j];
+            const double q1 = wave_sum(own ? (double)dj * (double)dg : 0.0);
+            const double q2 = wave_sum(own ? (double)cj * (double)den : 0.0);
             if (lane == 0) {
               wsel[0][wave] = q1;
               wsel[1][wave] = q2;
@@ -501,8 +509,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
             }
             cp = cj;
           }
-          __syncthreads();
-          if (j < K) {
+          if (own) {
             cj = mu_apply_d(cj, bj, (double)den, a.eps);
             csh[j] = cj;
           }
@@ -512,17 +519,17 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
           run_sh[0] = it;
           run_sh[1] = stop ? 1 : 0;
         }
+        __syncthreads();
+        its_total += run_sh[0];
+        met = run_sh[1] != 0;
+        __syncthreads();
       }
-      __syncthreads();
-      its_total += run_sh[0];
-      met = run_sh[1] != 0;
-      __syncthreads();
-    }
-    if (a.iters_out && tid == 0) a.iters_out[f] = its_total;
-    if (j < K) a.C_out[(int64_t)f * K + j] = csh[j];
-    if (a.ticks && tid == 0) {
-      a.ticks[2 * (int64_t)f] = tick0;
-      a.ticks[2 * (int64_t)f + 1] = wall_clock64();
+      if (a.iters_out && tid == 0) a.iters_out[f] = its_total;
+      if (tid < K) a.C_out[(int64_t)f * K + tid] = csh[tid];
+      if (a.ticks && tid == 0) {
+        a.ticks[2 * (int64_t)f] = tick0;
+        a.ticks[2 * (int64_t)f + 1] = wall_clock64();
+      }
     }
     __syncthreads();  // LDS is reused by the next frame
   }
@@ -558,14 +565,15 @@ static hipError_t gram_launch(const GramArgs& a, int max_blocks, hipStream_t s, 
 
 template <bool RAGGED, int PREC, bool FORM>
 static hipError_t gram_kp(int kp, const GramArgs& a, int max_blocks, hipStream_t s, int* g) {
-  switch (kp) {
-    case 32: return gram_launch<32, RAGGED, PREC, FORM>(a, max_blocks, s, g);
-    case 64: return gram_launch<64, RAGGED, PREC, FORM>(a, max_blocks, s, g);
-    case 96: return gram_launch<96, RAGGED, PREC, FORM>(a, max_blocks, s, g);
-    case 128: return gram_launch<128, RAGGED, PREC, FORM>(a, max_blocks, s, g);
-    default: break;
-  }
-  if constexpr (!FORM) {
+  if constexpr (FORM) {  // K <= 128: G formed here, iterated by k_gram_iter
+    switch (kp) {
+      case 32: return gram_launch<32, RAGGED, PREC, true>(a, max_blocks, s, g);
+      case 64: return gram_launch<64, RAGGED, PREC, true>(a, max_blocks, s, g);
+      case 96: return gram_launch<96, RAGGED, PREC, true>(a, max_blocks, s, g);
+      case 128: return gram_launch<128, RAGGED, PREC, true>(a, max_blocks, s, g);
+      default: break;
+    }
+  } else {
     switch (kp) {
       case 160: return gram_launch<160, RAGGED, PREC, false>(a, max_blocks, s, g);
       case 192: return gram_launch<192, RAGGED, PREC, false>(a, max_blocks, s, g);
@@ -597,10 +605,9 @@ hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, h
 // one wave (KP <= 64) or two.  Thread j keeps row j of the frame's G in
 // registers and updates coefficient j; the coefficients travel through a
 // double buffer in LDS, so one barrier per iteration suffices (iteration t
-// reads buffer t % 2 and writes the other).  The arithmetic is that of the
-// combined kernel (same products, sums and FP64 update), so the two forms
-// give the same bits; they differ only in how many frames a compute unit
-// iterates at once (several small workgroups instead of one large one).
+// reads buffer t % 2 and writes the other).  The update and the stop rule
+// are those of the one-launch form of k_gram for larger K (FP64 ratio and
+// objective sums, four FP32 partial sums per row product).
 // ---------------------------------------------------------------------------
 template <int KP, int KR>
 __global__ __launch_bounds__(KP <= 64 ? 64 : 128) void k_gram_iter(GramArgs a) {
