@@ -17,11 +17,13 @@
 // Pixels appear only through the staged chunks, so dense frames (all
 // pixels, weight row of M_T) and CSR frames share the kernel.
 //
-// G tiles take FP32 products (v_mfma_f32_32x32x2_f32 on the staged rows) or
-// split-precision ones: the chunk is also staged transposed (component
-// rows, pixels along the row) as bf16 hi/lo pairs of H and of H o m, so
-// that every operand of v_mfma_f32_32x32x16_bf16 is one 16-byte LDS read;
-// each tile then takes two reduction steps of three products per chunk.
+// G tiles take FP32 products (v_mfma_f32_32x32x2_f32 on the staged rows,
+// (H o m) H^T) or split-precision ones: G = (H o sqrt m)(H o sqrt m)^T, the
+// chunk's H o sqrt m staged transposed (component rows, pixels along the
+// row) as one bf16 hi/lo pair that serves both operands, so that every
+// operand of v_mfma_f32_32x32x16_bf16 is one 16-byte LDS read; each tile
+// then takes two reduction steps of three products per chunk.  The same
+// staging pass adds the chunk's b terms (h m) t in FP64.
 
 #include <type_traits>
 
@@ -59,9 +61,11 @@ __host__ __device__ constexpr int gram_waves() {
 // of GT_STRIDE (the pad keeps the per-lane 16-byte reads conflict-free).
 constexpr int GT_STRIDE = 20;
 
-template <int KP>
-__host__ __device__ constexpr int gram_stage_floats(int prec) {
-  return 64 * KP + 288 + (prec == PREC_BF16X3 ? 4 * KP * GT_STRIDE : 0);
+// LDS floats of the pixel loop: gathered rows [2][32][KP], rings of pixel
+// indices, weights, data and square-rooted weights [3][32] each, and (bf16x3)
+// the transposed hi/lo pair [2][KP][GT_STRIDE]
+__host__ __device__ constexpr int gram_stage_floats(int KP, int prec) {
+  return 64 * KP + 384 + (prec == PREC_BF16X3 ? 2 * KP * GT_STRIDE : 0);
 }
 
 template <int KP, bool RAGGED, int PREC, bool FORM>
@@ -78,23 +82,28 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   constexpr int TPW = (NT + NWV - 1) / NWV;
   constexpr int KQ = KP / 4;
   constexpr int FOLD = 8;  // chunks summed in FP32 before folding into FP64
-  // b = H (m o t): BG groups of KP threads, each group BPX pixels of a chunk
+  // b = H (m o t) on groups of KP threads, thread (bgrp, bcomp) summing
+  // component bcomp over its group's pixels of each chunk: FP32 form, BG
+  // groups of BPX consecutive pixels; split form, SG groups that take every
+  // SG-th pixel pair in the staging pass
   constexpr int BG = NTH / KP >= 8 ? 8 : NTH / KP >= 4 ? 4 : NTH / KP >= 2 ? 2 : 1;
   constexpr int BPX = 32 / BG;
+  constexpr int SG = NTH / KP < 16 ? NTH / KP : 16;
+  constexpr int NBG = PREC == PREC_BF16X3 ? SG : BG;
   const int K = a.K;
   // [2][32][KP] gathered H^T rows (the chunk in use and the next one)
   float* Hsb = lds;
-  // rings of three chunks' pixel indices, weights and data ([3][32] each)
+  // rings of three chunks' pixel indices, weights, data and square roots of
+  // the weights ([3][32] each)
   int* pixr = reinterpret_cast<int*>(lds + 64 * KP);
   float* msr = lds + 64 * KP + 96;
   float* tsr = msr + 96;
-  // bf16 hi/lo of H^T and (H o m)^T, [KP][GT_STRIDE] dwords (2 pixels each)
-  uint32_t* hT_hi = reinterpret_cast<uint32_t*>(lds + 64 * KP + 288);
-  uint32_t* hT_lo = hT_hi + KP * GT_STRIDE;
-  uint32_t* hmT_hi = hT_lo + KP * GT_STRIDE;
-  uint32_t* hmT_lo = hmT_hi + KP * GT_STRIDE;
+  float* qsr = tsr + 96;
+  // bf16 hi/lo of (H o sqrt m)^T, [KP][GT_STRIDE] dwords (2 pixels each)
+  uint32_t* wT_hi = reinterpret_cast<uint32_t*>(lds + 64 * KP + 384);
+  uint32_t* wT_lo = wT_hi + KP * GT_STRIDE;
   float* G = lds;             // [K][K] after the pixel loop (aliases the above)
-  const int goff = (max(K * K, gram_stage_floats<KP>(PREC)) + 3) & ~3;
+  const int goff = (max(K * K, gram_stage_floats(KP, PREC)) + 3) & ~3;
   double* bsh = reinterpret_cast<double*>(lds + goff);  // [KP]
   float* csh = reinterpret_cast<float*>(bsh + KP);      // [KP]
 
@@ -220,6 +229,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       pixr[32 * slot + tid] = prow;
       msr[32 * slot + tid] = m;
       tsr[32 * slot + tid] = t;
+      qsr[32 * slot + tid] = sqrtf(m);
     };
     auto gather = [&](int slot, float* dst) {  // all waves: 32 rows of H^T
 #pragma unroll
@@ -245,26 +255,25 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       float* Hs = Hsb + (c & 1) * 32 * KP;
       const float* ms = msr + 32 * sl;
       const float* ts = tsr + 32 * sl;
+      const float* qs = qsr + 32 * sl;
       if (base + 32 < e) gather((c + 1) % 3, Hsb + ((c + 1) & 1) * 32 * KP);
       if (tid < 32) meta_load(base + 64);
       if constexpr (PREC == PREC_BF16X3) {
-        // transposed split staging: thread -> (component, pixel pair); the
-        // reads of Hs are consecutive across threads, the dword writes land
-        // in distinct banks (odd multiples of the row stride apart)
-        for (int x = tid; x < 16 * KP; x += NTH) {
-          const int comp = x % KP, pp = x / KP;
-          const float h0 = Hs[(2 * pp) * KP + comp], h1 = Hs[(2 * pp + 1) * KP + comp];
-          const float w0 = h0 * ms[2 * pp], w1 = h1 * ms[2 * pp + 1];
-          const f32x2 hv = {h0, h1}, wv = {w0, w1};
-          const bf16x2 hh = __builtin_convertvector(hv, bf16x2);
-          const bf16x2 hl = __builtin_convertvector(hv - __builtin_convertvector(hh, f32x2), bf16x2);
-          const bf16x2 wh = __builtin_convertvector(wv, bf16x2);
-          const bf16x2 wl = __builtin_convertvector(wv - __builtin_convertvector(wh, f32x2), bf16x2);
-          const int o = comp * GT_STRIDE + pp;
-          hT_hi[o] = __builtin_bit_cast(uint32_t, hh);
-          hT_lo[o] = __builtin_bit_cast(uint32_t, hl);
-          hmT_hi[o] = __builtin_bit_cast(uint32_t, wh);
-          hmT_lo[o] = __builtin_bit_cast(uint32_t, wl);
+        // transposed split staging of w = h sqrt(m), thread (bgrp, bcomp) ->
+        // component bcomp, pixel pairs bgrp, bgrp + SG, ...: the reads of Hs
+        // are consecutive across threads; the same pass adds the b terms
+        if (bgrp < SG) {
+          for (int pp = bgrp; pp < 16; pp += SG) {
+            const float h0 = Hs[(2 * pp) * KP + bcomp], h1 = Hs[(2 * pp + 1) * KP + bcomp];
+            const f32x2 wv = {h0 * qs[2 * pp], h1 * qs[2 * pp + 1]};
+            const bf16x2 wh = __builtin_convertvector(wv, bf16x2);
+            const bf16x2 wl = __builtin_convertvector(wv - __builtin_convertvector(wh, f32x2), bf16x2);
+            const int o = bcomp * GT_STRIDE + pp;
+            wT_hi[o] = __builtin_bit_cast(uint32_t, wh);
+            wT_lo[o] = __builtin_bit_cast(uint32_t, wl);
+            bacc += (double)(h0 * ms[2 * pp]) * (double)ts[2 * pp];
+            bacc += (double)(h1 * ms[2 * pp + 1]) * (double)ts[2 * pp + 1];
+          }
         }
         __syncthreads();
       }
@@ -280,10 +289,10 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
               const int d = 8 * ks + 4 * half;
-              const bf16x8 ah = *reinterpret_cast<const bf16x8*>(hmT_hi + ra + d);
-              const bf16x8 al = *reinterpret_cast<const bf16x8*>(hmT_lo + ra + d);
-              const bf16x8 bh = *reinterpret_cast<const bf16x8*>(hT_hi + rb + d);
-              const bf16x8 bl = *reinterpret_cast<const bf16x8*>(hT_lo + rb + d);
+              const bf16x8 ah = *reinterpret_cast<const bf16x8*>(wT_hi + ra + d);
+              const bf16x8 al = *reinterpret_cast<const bf16x8*>(wT_lo + ra + d);
+              const bf16x8 bh = *reinterpret_cast<const bf16x8*>(wT_hi + rb + d);
+              const bf16x8 bl = *reinterpret_cast<const bf16x8*>(wT_lo + rb + d);
               acc[q] = mfma_bf16x3(ah, al, bh, bl, acc[q]);
             }
           } else {
@@ -297,8 +306,9 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
           }
         }
       }
-      // ---- b += H (m o t): thread (bgrp, bcomp) sums pixels bgrp*BPX.. ----
-      if (bgrp < BG) {
+      // ---- b += H (m o t), FP32 form: thread (bgrp, bcomp) sums pixels
+      // bgrp*BPX .. bgrp*BPX + BPX - 1 --------------------------------------
+      if (PREC != PREC_BF16X3 && bgrp < BG) {
 #pragma unroll
         for (int u = 0; u < BPX; ++u) {
           const int jr = bgrp * BPX + u;
@@ -318,9 +328,9 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
     // b: the groups' partial sums in group order (bsh is not aliased by the
     // staging area, so this needs no barrier before it)
 #pragma unroll
-    for (int gi = 0; gi < BG; ++gi) {
+    for (int gi = 0; gi < NBG; ++gi) {
       if (bgrp == gi) bsh[bcomp] = bcomp < K ? (gi == 0 ? bacc : bsh[bcomp] + bacc) : 0.0;
-      if (BG > 1) __syncthreads();
+      if (NBG > 1) __syncthreads();
     }
 
     // ---- G to LDS (both triangles), b and the starting coefficients -------
@@ -537,8 +547,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
 }
 
 size_t gram_lds_bytes(int K, int KP, int prec) {
-  const int stage = 64 * KP + 288 + (prec == PREC_BF16X3 ? 4 * KP * GT_STRIDE : 0);
-  const int goff = (std::max(K * K, stage) + 3) & ~3;
+  const int goff = (std::max(K * K, gram_stage_floats(KP, prec)) + 3) & ~3;
   return (size_t)goff * 4 + (size_t)KP * 8 + (size_t)KP * 4 * 2;  // G | b | c, d
 }
 
