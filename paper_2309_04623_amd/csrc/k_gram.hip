@@ -36,6 +36,10 @@ namespace nmf {
 __device__ __forceinline__ void gram_dma16(const void* src, float* lds) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
 }
+// The same with 4 bytes per lane: lane i's bytes land at lds + 4 i.
+__device__ __forceinline__ void gram_dma4(const void* src, float* lds) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+}
 
 template <int KP>
 __host__ __device__ constexpr int gram_tiles() {
@@ -61,11 +65,16 @@ __host__ __device__ constexpr int gram_waves() {
 // of GT_STRIDE (the pad keeps the per-lane 16-byte reads conflict-free).
 constexpr int GT_STRIDE = 20;
 
-// LDS floats of the pixel loop: gathered rows [2][32][KP], rings of pixel
-// indices, weights, data and square-rooted weights [3][32] each, and (bf16x3)
-// the transposed hi/lo pair [2][KP][GT_STRIDE]
+// Chunks of pixel rows gathered ahead of the one being reduced.
+__host__ __device__ constexpr int gram_ahead(int KP) { return KP <= 128 ? 2 : 1; }
+
+// LDS floats of the pixel loop: gathered rows [A+1][32][KP] (A chunks
+// ahead), rings of pixel indices, weights, data and square-rooted weights
+// [A+2][32] each, the raw pixel indices, weights and data as fetched
+// [2][3][32], and (bf16x3) the transposed hi/lo pair [2][KP][GT_STRIDE]
 __host__ __device__ constexpr int gram_stage_floats(int KP, int prec) {
-  return 64 * KP + 384 + (prec == PREC_BF16X3 ? 2 * KP * GT_STRIDE : 0);
+  return 32 * (gram_ahead(KP) + 1) * KP + 128 * (gram_ahead(KP) + 2) + 192 +
+         (prec == PREC_BF16X3 ? 2 * KP * GT_STRIDE : 0);
 }
 
 template <int KP, bool RAGGED, int PREC, bool FORM>
@@ -91,16 +100,19 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   constexpr int SG = NTH / KP < 16 ? NTH / KP : 16;
   constexpr int NBG = PREC == PREC_BF16X3 ? SG : BG;
   const int K = a.K;
-  // [2][32][KP] gathered H^T rows (the chunk in use and the next one)
+  constexpr int PF = gram_ahead(KP), NH = PF + 1, NM = PF + 2;
+  // [NH][32][KP] gathered H^T rows (the chunk in use and the next PF)
   float* Hsb = lds;
-  // rings of three chunks' pixel indices, weights, data and square roots of
-  // the weights ([3][32] each)
-  int* pixr = reinterpret_cast<int*>(lds + 64 * KP);
-  float* msr = lds + 64 * KP + 96;
-  float* tsr = msr + 96;
-  float* qsr = tsr + 96;
+  // rings of NM chunks' pixel indices, weights, data and square roots of
+  // the weights ([NM][32] each)
+  int* pixr = reinterpret_cast<int*>(lds + 32 * NH * KP);
+  float* msr = lds + 32 * NH * KP + 32 * NM;
+  float* tsr = msr + 32 * NM;
+  float* qsr = tsr + 32 * NM;
+  // two chunks' raw pixel indices, weights and data, as fetched ([2][3][32])
+  float* rawr = qsr + 32 * NM;
   // bf16 hi/lo of (H o sqrt m)^T, [KP][GT_STRIDE] dwords (2 pixels each)
-  uint32_t* wT_hi = reinterpret_cast<uint32_t*>(lds + 64 * KP + 384);
+  uint32_t* wT_hi = reinterpret_cast<uint32_t*>(rawr + 192);
   uint32_t* wT_lo = wT_hi + KP * GT_STRIDE;
   float* G = lds;             // [K][K] after the pixel loop (aliases the above)
   const int goff = (max(K * K, gram_stage_floats(KP, PREC)) + 3) & ~3;
@@ -166,13 +178,16 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
     double bacc = 0.0;
     int nfold = 0;
 
-    // Pixel chunks of 32 in a software pipeline: the rows of H^T of chunk
-    // c + 1 are gathered by LDS DMA (one 16-byte piece per lane, no
-    // registers) while chunk c is reduced, and the pixel indices, weights and
-    // data of chunk c + 2 are loaded then; each chunk ends with one barrier,
-    // which also retires its DMAs.  A pixel outside the frame or with an
-    // invalid index gathers row 0 (finite) under weight 0, so it adds
-    // exactly nothing.
+    // Pixel chunks of 32 in a software pipeline: while chunk c is reduced,
+    // the rows of H^T of chunk c + PF are gathered by LDS DMA (one 16-byte
+    // piece per lane, no registers), the raw pixel indices, weights and data
+    // of chunk c + PF + 2 are fetched by LDS DMA too, and those of chunk
+    // c + PF + 1 (fetched one chunk earlier) are checked into the ring.
+    // Each chunk ends with one barrier; with PF = 2 a wave waits there for
+    // its older DMAs only (vmcnt of the pieces it issued for chunk c + 2,
+    // which stay in flight).  A pixel outside the frame or with an invalid
+    // index gathers row 0 (finite) under weight 0, so it adds exactly
+    // nothing.
     int mp = 0;
     float mm = 0.f, mt = 0.f;
     auto meta_load = [&](int64_t b0) {  // threads < 32: chunk at b0
@@ -190,6 +205,35 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
           mm = a.MT[(int64_t)f * a.P + jj];
           mt = a.T[(int64_t)f * a.P + jj];
         }
+      }
+    };
+    auto meta_fetch = [&](int rs, int64_t b0) {  // threads < 32: chunk at b0, by DMA
+      const int64_t jj = min(b0 + tid, e - 1);  // lanes past the frame: any valid entry
+      float* rw = rawr + 96 * rs;
+      if constexpr (RAGGED) {
+        gram_dma4(a.pix + jj, rw);
+        if (a.wt) gram_dma4(a.wt + jj, rw + 32);
+        gram_dma4(a.val + jj, rw + 64);
+      } else {
+        gram_dma4(a.MT + (int64_t)f * a.P + jj, rw + 32);
+        gram_dma4(a.T + (int64_t)f * a.P + jj, rw + 64);
+      }
+    };
+    auto meta_take = [&](int rs, int64_t b0) {  // threads < 32: fetched values
+      const int64_t jj = b0 + tid;
+      const float* rw = rawr + 96 * rs;
+      mp = -1;
+      mm = 0.f;
+      mt = 0.f;
+      if (jj < e) {
+        if constexpr (RAGGED) {
+          mp = __builtin_bit_cast(int, rw[tid]);
+          mm = a.wt ? rw[32 + tid] : 1.0f;
+        } else {
+          mp = (int)jj;
+          mm = rw[32 + tid];
+        }
+        mt = rw[64 + tid];
       }
     };
     auto meta_store = [&](int slot, int64_t b0) {  // threads < 32: validated
@@ -238,26 +282,48 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
         gram_dma16(a.HT + lop_f32(pixr[32 * slot + jr], 4 * kq, KP), dst + 256 * i);
       }
     };
+    // pieces of 16 bytes a wave issues per chunk: at least NDMA
+    constexpr int NDMA = (KQ / 2) / NWV;
+    static_assert(NDMA >= 1 && NDMA < 64, "gather pieces per wave");
+    // barrier that leaves this wave's newest n VMEM operations in flight
+    // (LDS operations all complete); the empty asm statements keep the
+    // compiler from moving memory accesses across it
+    auto barrier_vm = [](auto n) {
+      constexpr int v = decltype(n)::value;
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_waitcnt((v & 15) | (7 << 4) | (0 << 8) | ((v >> 4) << 14));
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+    };
     if (s < e) {
       if (tid < 32) {
         meta_load(s);
         meta_store(0, s);
         meta_load(s + 32);
         meta_store(1, s + 32);
+        if constexpr (PF == 2) {
+          meta_load(s + 64);
+          meta_store(2, s + 64);
+        }
+        if (s + 32 * (PF + 1) < e) meta_fetch((PF + 1) & 1, s + 32 * (PF + 1));
       }
       __syncthreads();
       gather(0, Hsb);
+      if (PF == 2 && s + 32 < e) gather(1, Hsb + 32 * KP);
       __syncthreads();
     }
     int c = 0;
     for (int64_t base = s; base < e; base += 32, ++c) {
-      const int sl = c % 3;
-      float* Hs = Hsb + (c & 1) * 32 * KP;
+      const int sl = c % NM;
+      float* Hs = Hsb + (c % NH) * 32 * KP;
       const float* ms = msr + 32 * sl;
       const float* ts = tsr + 32 * sl;
       const float* qs = qsr + 32 * sl;
-      if (base + 32 < e) gather((c + 1) % 3, Hsb + ((c + 1) & 1) * 32 * KP);
-      if (tid < 32) meta_load(base + 64);
+      // chunk c + PF + 2's pixel data (before the gather: older DMAs land
+      // first)
+      if (tid < 32 && base + 32 * (PF + 2) < e) meta_fetch((c + PF) & 1, base + 32 * (PF + 2));
+      const bool ahead = base + 32 * PF < e;
+      if (ahead) gather((c + PF) % NM, Hsb + ((c + PF) % NH) * 32 * KP);
       if constexpr (PREC == PREC_BF16X3) {
         // transposed split staging of w = h sqrt(m), thread (bgrp, bcomp) ->
         // component bcomp, pixel pairs bgrp, bgrp + SG, ...: the reads of Hs
@@ -275,7 +341,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
             bacc += (double)(h1 * ms[2 * pp + 1]) * (double)ts[2 * pp + 1];
           }
         }
-        __syncthreads();
+        barrier_vm(std::integral_constant<int, 63>{});  // staged pairs visible
       }
 
       // ---- G tiles: G[mi-block, mj-block] += (H o m) H^T over the chunk ---
@@ -321,8 +387,16 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
         nfold = 0;
         fold();
       }
-      if (tid < 32) meta_store((c + 2) % 3, base + 64);
-      __syncthreads();
+      if (tid < 32) {
+        meta_take((c + PF + 1) & 1, base + 32 * (PF + 1));
+        meta_store((c + PF + 1) % NM, base + 32 * (PF + 1));
+      }
+      // chunk c + 1's rows landed (every wave's); with PF = 2 chunk c + 2's
+      // stay in flight
+      if (PF == 2 && ahead)
+        barrier_vm(std::integral_constant<int, NDMA>{});
+      else
+        barrier_vm(std::integral_constant<int, 0>{});
     }
     fold();
     // b: the groups' partial sums in group order (bsh is not aliased by the
