@@ -61,6 +61,22 @@ __host__ __device__ constexpr int gram_waves() {
   return KP <= 128 ? 4 : 8;
 }
 
+// How the split form spreads the tiles of G over the waves so that a wave
+// reads each 32-component block of the staged operand once per reduction
+// step and uses it for several tiles (the staged array is both operands):
+//   1 (4 or 3 blocks, four waves): wave w takes blocks p = w, q = w + 1,
+//     r = w + 2 (mod NB) and the tiles (p,p), (p,q) and, for NB = 4 and
+//     w < 2, (p,r); three waves for NB = 3;
+//   2 (7 blocks, eight waves): wave w < 7 takes the blocks of the line
+//     {w, w + 1, w + 3} (mod 7) of the Fano plane, whose seven lines hold
+//     every pair of blocks exactly once, and the tiles (w,w), (w,w+1),
+//     (w,w+3), (w+1,w+3);
+//   0: tile t to wave t mod NWV, each tile reading both its operands.
+template <int KP, int PREC>
+__host__ __device__ constexpr int gram_pattern() {
+  return PREC != PREC_BF16X3 ? 0 : (KP == 96 || KP == 128) ? 1 : KP == 224 ? 2 : 0;
+}
+
 // Transposed bf16 staging: a row per component, 16 dwords (32 pixels) used
 // of GT_STRIDE (the pad keeps the per-lane 16-byte reads conflict-free).
 constexpr int GT_STRIDE = 20;
@@ -70,11 +86,12 @@ __host__ __device__ constexpr int gram_ahead(int KP) { return KP <= 128 ? 2 : 1;
 
 // LDS floats of the pixel loop: gathered rows [A+1][32][KP] (A chunks
 // ahead), rings of pixel indices, weights, data and square-rooted weights
-// [A+2][32] each, the raw pixel indices, weights and data as fetched
-// [2][3][32], and (bf16x3) the transposed hi/lo pair [2][KP][GT_STRIDE]
+// [A+2+L][32] each (L = 1 for the split form, which stages a chunk ahead),
+// the raw pixel indices, weights and data as fetched [2][3][32], and
+// (bf16x3) two transposed hi/lo pairs [2][2][KP][GT_STRIDE]
 __host__ __device__ constexpr int gram_stage_floats(int KP, int prec) {
-  return 32 * (gram_ahead(KP) + 1) * KP + 128 * (gram_ahead(KP) + 2) + 192 +
-         (prec == PREC_BF16X3 ? 2 * KP * GT_STRIDE : 0);
+  return 32 * (gram_ahead(KP) + 1) * KP + 128 * (gram_ahead(KP) + 2 + (prec == PREC_BF16X3)) +
+         192 + (prec == PREC_BF16X3 ? 4 * KP * GT_STRIDE : 0);
 }
 
 template <int KP, bool RAGGED, int PREC, bool FORM>
@@ -88,7 +105,11 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   constexpr int NT = gram_tiles<KP>();
   constexpr int NWV = gram_waves<KP>();
   constexpr int NTH = 64 * NWV;
-  constexpr int TPW = (NT + NWV - 1) / NWV;
+  constexpr int GP = gram_pattern<KP, PREC>();
+  constexpr int TPW = GP == 1 ? (NB == 4 ? 3 : 2) : GP == 2 ? 4 : (NT + NWV - 1) / NWV;
+  // blocks of a pattern tile: slot s multiplies block LA[s] by block LB[s]
+  constexpr int LA[4] = {0, 0, 0, 1};
+  constexpr int LB[4] = {0, 1, 2, 2};
   constexpr int KQ = KP / 4;
   constexpr int FOLD = 8;  // chunks summed in FP32 before folding into FP64
   // b = H (m o t) on groups of KP threads, thread (bgrp, bcomp) summing
@@ -100,7 +121,11 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   constexpr int SG = NTH / KP < 16 ? NTH / KP : 16;
   constexpr int NBG = PREC == PREC_BF16X3 ? SG : BG;
   const int K = a.K;
-  constexpr int PF = gram_ahead(KP), NH = PF + 1, NM = PF + 2;
+  // PF: chunks gathered ahead of their first use; LEAD: chunks staged ahead
+  // of the one multiplied (split form); GA: chunks gathered ahead of the one
+  // multiplied
+  constexpr int PF = gram_ahead(KP), LEAD = PREC == PREC_BF16X3 ? 1 : 0, GA = PF + LEAD;
+  constexpr int NH = PF + 1, NM = GA + 2;
   // [NH][32][KP] gathered H^T rows (the chunk in use and the next PF)
   float* Hsb = lds;
   // rings of NM chunks' pixel indices, weights, data and square roots of
@@ -111,9 +136,9 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   float* qsr = tsr + 32 * NM;
   // two chunks' raw pixel indices, weights and data, as fetched ([2][3][32])
   float* rawr = qsr + 32 * NM;
-  // bf16 hi/lo of (H o sqrt m)^T, [KP][GT_STRIDE] dwords (2 pixels each)
-  uint32_t* wT_hi = reinterpret_cast<uint32_t*>(rawr + 192);
-  uint32_t* wT_lo = wT_hi + KP * GT_STRIDE;
+  // two buffers of bf16 hi/lo of (H o sqrt m)^T, [2][2][KP][GT_STRIDE]
+  // dwords (2 pixels each)
+  uint32_t* wT = reinterpret_cast<uint32_t*>(rawr + 192);
   float* G = lds;             // [K][K] after the pixel loop (aliases the above)
   const int goff = (max(K * K, gram_stage_floats(KP, PREC)) + 3) & ~3;
   double* bsh = reinterpret_cast<double*>(lds + goff);  // [KP]
@@ -123,14 +148,37 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   const int col = lane & 31, half = lane >> 5;
   const int bgrp = tid / KP, bcomp = tid - bgrp * KP;
   int tmi[TPW], tmj[TPW];
+  int blk[3] = {0, 0, 0};  // the wave's blocks (patterns 1 and 2)
+  if constexpr (GP == 0) {
 #pragma unroll
-  for (int q = 0; q < TPW; ++q) {
-    const int idx = wave + NWV * q;
-    if (idx < NT) {
-      tile_of(idx, NB, tmi[q], tmj[q]);
+    for (int q = 0; q < TPW; ++q) {
+      const int idx = wave + NWV * q;
+      if (idx < NT) {
+        tile_of(idx, NB, tmi[q], tmj[q]);
+      } else {
+        tmi[q] = -1;
+        tmj[q] = -1;
+      }
+    }
+  } else {
+    static_assert(GP != 1 || (NWV == 4 && (NB == 3 || NB == 4)), "row pattern");
+    static_assert(GP != 2 || (NWV == 8 && NB == 7), "Fano pattern");
+    int ntl;
+    if constexpr (GP == 1) {
+      blk[0] = wave;
+      blk[1] = (wave + 1) % NB;
+      blk[2] = (wave + 2) % NB;
+      ntl = NB == 4 ? (wave < 2 ? 3 : 2) : (wave < 3 ? 2 : 0);
     } else {
-      tmi[q] = -1;
-      tmj[q] = -1;
+      blk[0] = wave;
+      blk[1] = (wave + 1) % 7;
+      blk[2] = (wave + 3) % 7;
+      ntl = wave < 7 ? 4 : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      tmi[q] = q < ntl ? blk[LA[q]] : -1;
+      tmj[q] = q < ntl ? blk[LB[q]] : -1;
     }
   }
   const uint64_t key = sm_key(a.seed, 2);
@@ -178,16 +226,17 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
     double bacc = 0.0;
     int nfold = 0;
 
-    // Pixel chunks of 32 in a software pipeline: while chunk c is reduced,
-    // the rows of H^T of chunk c + PF are gathered by LDS DMA (one 16-byte
-    // piece per lane, no registers), the raw pixel indices, weights and data
-    // of chunk c + PF + 2 are fetched by LDS DMA too, and those of chunk
-    // c + PF + 1 (fetched one chunk earlier) are checked into the ring.
+    // Pixel chunks of 32 in a software pipeline: while the tiles of chunk c
+    // are multiplied, the split form stages chunk c + 1 (into the other
+    // buffer), the rows of H^T of chunk c + GA are gathered by LDS DMA (one
+    // 16-byte piece per lane, no registers), the raw pixel indices, weights
+    // and data of chunk c + GA + 2 are fetched by LDS DMA too, and those of
+    // chunk c + GA + 1 (fetched one chunk earlier) are checked into the ring.
     // Each chunk ends with one barrier; with PF = 2 a wave waits there for
-    // its older DMAs only (vmcnt of the pieces it issued for chunk c + 2,
-    // which stay in flight).  A pixel outside the frame or with an invalid
-    // index gathers row 0 (finite) under weight 0, so it adds exactly
-    // nothing.
+    // its older DMAs only (vmcnt of the pieces it issued this chunk, first
+    // used two chunks later, stay in flight).  A pixel outside the frame or
+    // with an invalid index gathers row 0 (finite) under weight 0, so it
+    // adds exactly nothing.
     int mp = 0;
     float mm = 0.f, mt = 0.f;
     auto meta_load = [&](int64_t b0) {  // threads < 32: chunk at b0
@@ -295,90 +344,137 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       __builtin_amdgcn_s_barrier();
       asm volatile("" ::: "memory");
     };
+    // split form: transposed staging of w = h sqrt(m) of one chunk into
+    // buffer wb, thread (bgrp, bcomp) -> component bcomp, pixel pairs bgrp,
+    // bgrp + SG, ...: the reads of Hs are consecutive across threads; the
+    // same pass adds the chunk's b terms
+    auto stage = [&](const float* Hsrc, int slot, int wb) {
+      const float* msl = msr + 32 * slot;
+      const float* tsl = tsr + 32 * slot;
+      const float* qsl = qsr + 32 * slot;
+      uint32_t* dhi = wT + wb * 2 * KP * GT_STRIDE;
+      uint32_t* dlo = dhi + KP * GT_STRIDE;
+      if (bgrp < SG) {
+        for (int pp = bgrp; pp < 16; pp += SG) {
+          const float h0 = Hsrc[(2 * pp) * KP + bcomp], h1 = Hsrc[(2 * pp + 1) * KP + bcomp];
+          const f32x2 wv = {h0 * qsl[2 * pp], h1 * qsl[2 * pp + 1]};
+          const bf16x2 wh = __builtin_convertvector(wv, bf16x2);
+          const bf16x2 wl = __builtin_convertvector(wv - __builtin_convertvector(wh, f32x2), bf16x2);
+          const int o = bcomp * GT_STRIDE + pp;
+          dhi[o] = __builtin_bit_cast(uint32_t, wh);
+          dlo[o] = __builtin_bit_cast(uint32_t, wl);
+          bacc += (double)(h0 * msl[2 * pp]) * (double)tsl[2 * pp];
+          bacc += (double)(h1 * msl[2 * pp + 1]) * (double)tsl[2 * pp + 1];
+        }
+      }
+    };
     if (s < e) {
       if (tid < 32) {
-        meta_load(s);
-        meta_store(0, s);
-        meta_load(s + 32);
-        meta_store(1, s + 32);
-        if constexpr (PF == 2) {
-          meta_load(s + 64);
-          meta_store(2, s + 64);
+#pragma unroll
+        for (int x = 0; x <= GA; ++x) {
+          meta_load(s + 32 * x);
+          meta_store(x, s + 32 * x);
         }
-        if (s + 32 * (PF + 1) < e) meta_fetch((PF + 1) & 1, s + 32 * (PF + 1));
+        if (s + 32 * (GA + 1) < e) meta_fetch((GA + 1) & 1, s + 32 * (GA + 1));
       }
       __syncthreads();
-      gather(0, Hsb);
-      if (PF == 2 && s + 32 < e) gather(1, Hsb + 32 * KP);
+#pragma unroll
+      for (int x = 0; x < GA; ++x)
+        if (s + 32 * x < e) gather(x, Hsb + x * 32 * KP);
       __syncthreads();
+      if constexpr (LEAD == 1) {
+        stage(Hsb, 0, 0);
+        __syncthreads();
+      }
     }
     int c = 0;
     for (int64_t base = s; base < e; base += 32, ++c) {
       const int sl = c % NM;
-      float* Hs = Hsb + (c % NH) * 32 * KP;
+      const float* Hs = Hsb + (c % NH) * 32 * KP;
       const float* ms = msr + 32 * sl;
       const float* ts = tsr + 32 * sl;
-      const float* qs = qsr + 32 * sl;
-      // chunk c + PF + 2's pixel data (before the gather: older DMAs land
+      // chunk c + GA + 2's pixel data (before the gather: older DMAs land
       // first)
-      if (tid < 32 && base + 32 * (PF + 2) < e) meta_fetch((c + PF) & 1, base + 32 * (PF + 2));
-      const bool ahead = base + 32 * PF < e;
-      if (ahead) gather((c + PF) % NM, Hsb + ((c + PF) % NH) * 32 * KP);
-      if constexpr (PREC == PREC_BF16X3) {
-        // transposed split staging of w = h sqrt(m), thread (bgrp, bcomp) ->
-        // component bcomp, pixel pairs bgrp, bgrp + SG, ...: the reads of Hs
-        // are consecutive across threads; the same pass adds the b terms
-        if (bgrp < SG) {
-          for (int pp = bgrp; pp < 16; pp += SG) {
-            const float h0 = Hs[(2 * pp) * KP + bcomp], h1 = Hs[(2 * pp + 1) * KP + bcomp];
-            const f32x2 wv = {h0 * qs[2 * pp], h1 * qs[2 * pp + 1]};
-            const bf16x2 wh = __builtin_convertvector(wv, bf16x2);
-            const bf16x2 wl = __builtin_convertvector(wv - __builtin_convertvector(wh, f32x2), bf16x2);
-            const int o = bcomp * GT_STRIDE + pp;
-            wT_hi[o] = __builtin_bit_cast(uint32_t, wh);
-            wT_lo[o] = __builtin_bit_cast(uint32_t, wl);
-            bacc += (double)(h0 * ms[2 * pp]) * (double)ts[2 * pp];
-            bacc += (double)(h1 * ms[2 * pp + 1]) * (double)ts[2 * pp + 1];
-          }
-        }
-        barrier_vm(std::integral_constant<int, 63>{});  // staged pairs visible
-      }
+      if (tid < 32 && base + 32 * (GA + 2) < e) meta_fetch((c + GA) & 1, base + 32 * (GA + 2));
+      const bool ahead = base + 32 * GA < e;
+      if (ahead) gather((c + GA) % NM, Hsb + ((c + GA) % NH) * 32 * KP);
 
       // ---- G tiles: G[mi-block, mj-block] += (H o m) H^T over the chunk ---
+      auto tiles = [&]() {
+        if constexpr (GP != 0) {
+          // each of the wave's blocks read once per reduction step
+          const uint32_t* whi = wT + (c & 1) * 2 * KP * GT_STRIDE;
+          const uint32_t* wlo = whi + KP * GT_STRIDE;
 #pragma unroll
-      for (int q = 0; q < TPW; ++q) {
-        if (tmi[q] >= 0) {
-          if constexpr (PREC == PREC_BF16X3) {
-            // reduction step ks covers pixels 16 ks .. 16 ks + 15; lane half
-            // h holds pixels 16 ks + 8 h .. + 7 (dwords 8 ks + 4 h .. + 3)
-            const int ra = (32 * tmi[q] + col) * GT_STRIDE, rb = (32 * tmj[q] + col) * GT_STRIDE;
+          for (int ks = 0; ks < 2; ++ks) {
+            const int d = 8 * ks + 4 * half;
+            bf16x8 bh[3], bl[3];
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-              const int d = 8 * ks + 4 * half;
-              const bf16x8 ah = *reinterpret_cast<const bf16x8*>(wT_hi + ra + d);
-              const bf16x8 al = *reinterpret_cast<const bf16x8*>(wT_lo + ra + d);
-              const bf16x8 bh = *reinterpret_cast<const bf16x8*>(wT_hi + rb + d);
-              const bf16x8 bl = *reinterpret_cast<const bf16x8*>(wT_lo + rb + d);
-              acc[q] = mfma_bf16x3(ah, al, bh, bl, acc[q]);
+            for (int l = 0; l < 3; ++l) {
+              // block 0 serves every tile, block l > 0 the tiles of slot l on
+              const bool used = l == 0 ? tmi[0] >= 0 : (l < TPW && tmj[l] >= 0);
+              const int r = (32 * blk[l] + col) * GT_STRIDE + d;
+              bh[l] = used ? *reinterpret_cast<const bf16x8*>(whi + r) : bf16x8{};
+              bl[l] = used ? *reinterpret_cast<const bf16x8*>(wlo + r) : bf16x8{};
             }
-          } else {
-            const float* ha = Hs + 32 * tmi[q] + col;
-            const float* hb = Hs + 32 * tmj[q] + col;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-              const int jr = 2 * u + half;
-              acc[q] = mfma_f32(ha[jr * KP] * ms[jr], hb[jr * KP], acc[q]);
+            for (int q = 0; q < TPW; ++q)
+              if (tmi[q] >= 0)
+                acc[q] = mfma_bf16x3(bh[LA[q]], bl[LA[q]], bh[LB[q]], bl[LB[q]], acc[q]);
+          }
+          return;
+        }
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+          if (tmi[q] >= 0) {
+            if constexpr (PREC == PREC_BF16X3 && GP == 0) {
+              // reduction step ks covers pixels 16 ks .. 16 ks + 15; lane
+              // half h holds pixels 16 ks + 8 h .. + 7 (dwords 8 ks + 4 h ..)
+              const uint32_t* whi = wT + (c & 1) * 2 * KP * GT_STRIDE;
+              const uint32_t* wlo = whi + KP * GT_STRIDE;
+              const int ra = (32 * tmi[q] + col) * GT_STRIDE, rb = (32 * tmj[q] + col) * GT_STRIDE;
+#pragma unroll
+              for (int ks = 0; ks < 2; ++ks) {
+                const int d = 8 * ks + 4 * half;
+                const bf16x8 ah = *reinterpret_cast<const bf16x8*>(whi + ra + d);
+                const bf16x8 al = *reinterpret_cast<const bf16x8*>(wlo + ra + d);
+                const bf16x8 bh = *reinterpret_cast<const bf16x8*>(whi + rb + d);
+                const bf16x8 bl = *reinterpret_cast<const bf16x8*>(wlo + rb + d);
+                acc[q] = mfma_bf16x3(ah, al, bh, bl, acc[q]);
+              }
+            } else {
+              const float* ha = Hs + 32 * tmi[q] + col;
+              const float* hb = Hs + 32 * tmj[q] + col;
+#pragma unroll
+              for (int u = 0; u < 16; ++u) {
+                const int jr = 2 * u + half;
+                acc[q] = mfma_f32(ha[jr * KP] * ms[jr], hb[jr * KP], acc[q]);
+              }
             }
           }
         }
-      }
-      // ---- b += H (m o t), FP32 form: thread (bgrp, bcomp) sums pixels
-      // bgrp*BPX .. bgrp*BPX + BPX - 1 --------------------------------------
-      if (PREC != PREC_BF16X3 && bgrp < BG) {
+      };
+      if constexpr (PREC == PREC_BF16X3) {
+        // the two waves of a SIMD (wave w and w + 4 of eight) take the two
+        // parts in opposite orders, so one multiplies while the other stages
+        const bool next = base + 32 < e;
+        if (NWV == 8 && (wave & 4)) {
+          if (next) stage(Hsb + ((c + 1) % NH) * 32 * KP, (c + 1) % NM, (c + 1) & 1);
+          tiles();
+        } else {
+          tiles();
+          if (next) stage(Hsb + ((c + 1) % NH) * 32 * KP, (c + 1) % NM, (c + 1) & 1);
+        }
+      } else {
+        tiles();
+        // ---- b += H (m o t), FP32 form: thread (bgrp, bcomp) sums pixels
+        // bgrp*BPX .. bgrp*BPX + BPX - 1 ------------------------------------
+        if (bgrp < BG) {
 #pragma unroll
-        for (int u = 0; u < BPX; ++u) {
-          const int jr = bgrp * BPX + u;
-          bacc += (double)(Hs[jr * KP + bcomp] * ms[jr]) * (double)ts[jr];
+          for (int u = 0; u < BPX; ++u) {
+            const int jr = bgrp * BPX + u;
+            bacc += (double)(Hs[jr * KP + bcomp] * ms[jr]) * (double)ts[jr];
+          }
         }
       }
       // Two-level sum: FOLD chunks in the FP32 MFMA accumulators, then into
@@ -388,11 +484,11 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
         fold();
       }
       if (tid < 32) {
-        meta_take((c + PF + 1) & 1, base + 32 * (PF + 1));
-        meta_store((c + PF + 1) % NM, base + 32 * (PF + 1));
+        meta_take((c + GA + 1) & 1, base + 32 * (GA + 1));
+        meta_store((c + GA + 1) % NM, base + 32 * (GA + 1));
       }
-      // chunk c + 1's rows landed (every wave's); with PF = 2 chunk c + 2's
-      // stay in flight
+      // the rows used next chunk landed (every wave's); with PF = 2 those
+      // gathered this chunk stay in flight
       if (PF == 2 && ahead)
         barrier_vm(std::integral_constant<int, NDMA>{});
       else
