@@ -87,7 +87,10 @@ enum nmf_flags {
                                 passes on first use of a shape and cache the
                                 fastest in the handle (a different split
                                 changes the summation order, so results may
-                                differ in the last bits from the default)   */
+                                differ in the last bits from the default);
+                                for the masked-Gram projection, the depth of
+                                its row gathers (same results), timed on the
+                                call's own inputs (the call synchronises)  */
 };
 
 /* Iteration parameters.  Fill with nmf_params_default() first. */
@@ -390,8 +393,10 @@ int nmf_warmstart_infer(nmf_handle h, const float* state, const float* X, const 
                         int64_t f, int32_t k, int32_t precision, float* C_out, void* stream);
 
 /* Launch shapes chosen so far by NMF_F_AUTOTUNE: writes up to cap lines of
- * "pass n p k precision: waves pipeline splits time_us" into buf [host].
- * Returns the number of cached entries.                                     */
+ * "pass n p k precision: waves pipeline splits time_us" into buf [host]
+ * (masked-Gram entries, keyed "gram.*": pipeline = chunks of rows gathered
+ * ahead, time of the whole projection).  Returns the number of cached
+ * entries.                                                                  */
 int nmf_autotune_report(nmf_handle h, char* buf, size_t cap);
 
 /* ---- live kernel timing ----------------------------------------------------

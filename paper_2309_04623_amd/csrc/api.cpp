@@ -763,6 +763,9 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
   a.bf = bf;
   a.cf = cf;
   a.visits = visits;
+  // rows of H^T gathered two chunks ahead of their use, one for the split
+  // form above K = 128 (measured faster there; NMF_F_AUTOTUNE times both)
+  a.ahead = (KP > 128 && c.prm->precision == NMF_PREC_BF16X3) ? 1 : 2;
   const FactorFillArgs fa = fill_args(Hf, c.H, 1, 0, 1, K);
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     hipError_t e;
@@ -781,6 +784,46 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
     if (!two_phase) return hipSuccess;
     return timed(h, NMF_K_PROJECT, s, [&]() { return launch_gram_iter(KP, a, s); });
   };
+  // Autotuning: the gather depth of the pixel loop (rows of H^T one or two
+  // chunks ahead of their use) timed on this call's own inputs, the second
+  // of two eager runs of the whole sequence per candidate; the choice is
+  // cached per shape.  Both depths compute the same bits, and every output
+  // is written again by the run that follows.
+  if (c.prm->flags & NMF_F_AUTOTUNE) {
+    const std::string tkey =
+        key_of(ragged ? "gram.csr" : "gram.dense",
+               {(uint64_t)K, (uint64_t)c.p, (uint64_t)c.f, (uint64_t)c.nnz,
+                (uint64_t)c.prm->precision, (uint64_t)c.prm->max_iter, (uint64_t)ce,
+                (uint64_t)(warm ? 1 : 0)});
+    auto it = h->tuned.find(tkey);
+    if (it != h->tuned.end()) {
+      a.ahead = it->second.pipe;
+    } else {
+      hipEvent_t e0, e1;
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      float best = 1e30f;
+      int best_pf = 2;
+      for (int pf : {1, 2}) {
+        a.ahead = pf;
+        HIP_TRY(enqueue(s));
+        HIP_TRY(hipEventRecord(e0, s));
+        HIP_TRY(enqueue(s));
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms * 1e3f < best) {
+          best = ms * 1e3f;
+          best_pf = pf;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      a.ahead = best_pf;
+      h->tuned[tkey] = {KP <= 128 ? 4 : 8, best_pf, 1, best};
+    }
+  }
   const std::string key =
       key_of(ragged ? "gramR" : "gramD",
              {(uint64_t)c.H, (uint64_t)K, (uint64_t)c.p, (uint64_t)c.f, (uint64_t)c.T,
@@ -791,7 +834,8 @@ int project_gram(nmf_handle h, const GramCall& c, hipStream_t s, nmf_report* rep
               (uint64_t)__builtin_bit_cast(uint32_t, c.prm->floor_eps), (uint64_t)ce,
               __builtin_bit_cast(uint64_t, a.tol2), (uint64_t)its, (uint64_t)Hf.m,
               (uint64_t)queue, (uint64_t)stat, (uint64_t)order, (uint64_t)sort_tmp,
-              (uint64_t)fb, (uint64_t)Gf, (uint64_t)bf, (uint64_t)cf, (uint64_t)visits});
+              (uint64_t)fb, (uint64_t)Gf, (uint64_t)bf, (uint64_t)cf, (uint64_t)visits,
+              (uint64_t)a.ahead});
   HIP_TRY(hipEventRecord(h->ev0, s));
   HIP_TRY(run_graph(h, key, s, enqueue));
   HIP_TRY(hipEventRecord(h->ev1, s));

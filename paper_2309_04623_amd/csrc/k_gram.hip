@@ -81,21 +81,25 @@ __host__ __device__ constexpr int gram_pattern() {
 // of GT_STRIDE (the pad keeps the per-lane 16-byte reads conflict-free).
 constexpr int GT_STRIDE = 20;
 
-// Chunks of pixel rows gathered ahead of the one being reduced.
-__host__ __device__ constexpr int gram_ahead(int KP) { return KP <= 128 ? 2 : 1; }
+// Rows of each staged bf16 array: KP, or for KP > 128 only K (components
+// K.. are never staged: the tiles that read past row K land in rows and
+// columns of G that are never used, and stay inside the allocation, which
+// holds at least 4 KP floats after the staging area).
+__host__ __device__ constexpr int gram_staged_rows(int K, int KP) { return KP <= 128 ? KP : K; }
 
-// LDS floats of the pixel loop: gathered rows [A+1][32][KP] (A chunks
-// ahead), rings of pixel indices, weights, data and square-rooted weights
-// [A+2+L][32] each (L = 1 for the split form, which stages a chunk ahead),
-// the raw pixel indices, weights and data as fetched [2][3][32], and
-// (bf16x3) two transposed hi/lo pairs [2][2][KP][GT_STRIDE]
-__host__ __device__ constexpr int gram_stage_floats(int KP, int prec) {
-  return 32 * (gram_ahead(KP) + 1) * KP + 128 * (gram_ahead(KP) + 2 + (prec == PREC_BF16X3)) +
-         192 + (prec == PREC_BF16X3 ? 4 * KP * GT_STRIDE : 0);
+// LDS floats of the pixel loop with rows gathered PF chunks ahead of their
+// first use: gathered rows [PF+1][32][KP], rings of pixel indices, weights,
+// data and square-rooted weights [PF+2][32] each, the raw pixel indices,
+// weights and data as fetched [2][3][32], and (bf16x3) two transposed hi/lo
+// pairs [2][2][rows][GT_STRIDE]
+__host__ __device__ constexpr int gram_stage_floats(int K, int KP, int prec, int pf) {
+  return 32 * (pf + 1) * KP + 128 * (pf + 2) + 192 +
+         (prec == PREC_BF16X3 ? 4 * gram_staged_rows(K, KP) * GT_STRIDE : 0);
 }
 
-template <int KP, bool RAGGED, int PREC, bool FORM>
+template <int KP, bool RAGGED, int PREC, bool FORM, int PF>
 __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
+  static_assert(PF == 1 || PF == 2, "rows gathered one or two chunks ahead");
   static_assert(!FORM || KP <= 128, "the two-phase form keeps a row of G per lane");
   static_assert(FORM || KP > 128, "K <= 128 iterates in k_gram_iter");
   extern __shared__ __align__(16) float lds[];
@@ -124,8 +128,10 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   // PF: chunks gathered ahead of their first use; LEAD: chunks staged ahead
   // of the one multiplied (split form); GA: chunks gathered ahead of the one
   // multiplied
-  constexpr int PF = gram_ahead(KP), LEAD = PREC == PREC_BF16X3 ? 1 : 0, GA = PF + LEAD;
-  constexpr int NH = PF + 1, NM = GA + 2;
+  constexpr int LEAD = PREC == PREC_BF16X3 ? 1 : 0, GA = PF + LEAD;
+  // ring slots: chunks c + LEAD .. c + GA + 1 are live while chunk c is
+  // multiplied (the split form no longer needs chunk c's)
+  constexpr int NH = PF + 1, NM = GA + 2 - LEAD;
   // [NH][32][KP] gathered H^T rows (the chunk in use and the next PF)
   float* Hsb = lds;
   // rings of NM chunks' pixel indices, weights, data and square roots of
@@ -136,11 +142,12 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   float* qsr = tsr + 32 * NM;
   // two chunks' raw pixel indices, weights and data, as fetched ([2][3][32])
   float* rawr = qsr + 32 * NM;
-  // two buffers of bf16 hi/lo of (H o sqrt m)^T, [2][2][KP][GT_STRIDE]
+  // two buffers of bf16 hi/lo of (H o sqrt m)^T, [2][2][rows][GT_STRIDE]
   // dwords (2 pixels each)
   uint32_t* wT = reinterpret_cast<uint32_t*>(rawr + 192);
+  const int WB = gram_staged_rows(K, KP) * GT_STRIDE;  // dwords of one hi or lo array
   float* G = lds;             // [K][K] after the pixel loop (aliases the above)
-  const int goff = (max(K * K, gram_stage_floats(KP, PREC)) + 3) & ~3;
+  const int goff = (max(K * K, gram_stage_floats(K, KP, PREC, PF)) + 3) & ~3;
   double* bsh = reinterpret_cast<double*>(lds + goff);  // [KP]
   float* csh = reinterpret_cast<float*>(bsh + KP);      // [KP]
 
@@ -331,9 +338,9 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
         gram_dma16(a.HT + lop_f32(pixr[32 * slot + jr], 4 * kq, KP), dst + 256 * i);
       }
     };
-    // pieces of 16 bytes a wave issues per chunk: at least NDMA
+    // DMA instructions a wave issues per chunk: at least NDMA
     constexpr int NDMA = (KQ / 2) / NWV;
-    static_assert(NDMA >= 1 && NDMA < 64, "gather pieces per wave");
+    static_assert(NDMA >= 1 && NDMA < 64, "gather instructions per wave");
     // barrier that leaves this wave's newest n VMEM operations in flight
     // (LDS operations all complete); the empty asm statements keep the
     // compiler from moving memory accesses across it
@@ -352,9 +359,10 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       const float* msl = msr + 32 * slot;
       const float* tsl = tsr + 32 * slot;
       const float* qsl = qsr + 32 * slot;
-      uint32_t* dhi = wT + wb * 2 * KP * GT_STRIDE;
-      uint32_t* dlo = dhi + KP * GT_STRIDE;
-      if (bgrp < SG) {
+      uint32_t* dhi = wT + wb * 2 * WB;
+      uint32_t* dlo = dhi + WB;
+      // components K.. are not staged (see gram_staged_rows)
+      if (bgrp < SG && bcomp < K) {
         for (int pp = bgrp; pp < 16; pp += SG) {
           const float h0 = Hsrc[(2 * pp) * KP + bcomp], h1 = Hsrc[(2 * pp + 1) * KP + bcomp];
           const f32x2 wv = {h0 * qsl[2 * pp], h1 * qsl[2 * pp + 1]};
@@ -403,8 +411,8 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       auto tiles = [&]() {
         if constexpr (GP != 0) {
           // each of the wave's blocks read once per reduction step
-          const uint32_t* whi = wT + (c & 1) * 2 * KP * GT_STRIDE;
-          const uint32_t* wlo = whi + KP * GT_STRIDE;
+          const uint32_t* whi = wT + (c & 1) * 2 * WB;
+          const uint32_t* wlo = whi + WB;
 #pragma unroll
           for (int ks = 0; ks < 2; ++ks) {
             const int d = 8 * ks + 4 * half;
@@ -430,8 +438,8 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
             if constexpr (PREC == PREC_BF16X3 && GP == 0) {
               // reduction step ks covers pixels 16 ks .. 16 ks + 15; lane
               // half h holds pixels 16 ks + 8 h .. + 7 (dwords 8 ks + 4 h ..)
-              const uint32_t* whi = wT + (c & 1) * 2 * KP * GT_STRIDE;
-              const uint32_t* wlo = whi + KP * GT_STRIDE;
+              const uint32_t* whi = wT + (c & 1) * 2 * WB;
+              const uint32_t* wlo = whi + WB;
               const int ra = (32 * tmi[q] + col) * GT_STRIDE, rb = (32 * tmj[q] + col) * GT_STRIDE;
 #pragma unroll
               for (int ks = 0; ks < 2; ++ks) {
@@ -469,7 +477,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
         tiles();
         // ---- b += H (m o t), FP32 form: thread (bgrp, bcomp) sums pixels
         // bgrp*BPX .. bgrp*BPX + BPX - 1 ------------------------------------
-        if (bgrp < BG) {
+        if (bgrp < BG && bcomp < K) {
 #pragma unroll
           for (int u = 0; u < BPX; ++u) {
             const int jr = bgrp * BPX + u;
@@ -716,15 +724,15 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   if (bad) atomicOr(a.status, bad);
 }
 
-size_t gram_lds_bytes(int K, int KP, int prec) {
-  const int goff = (std::max(K * K, gram_stage_floats(KP, prec)) + 3) & ~3;
+size_t gram_lds_bytes(int K, int KP, int prec, int ahead) {
+  const int goff = (std::max(K * K, gram_stage_floats(K, KP, prec, ahead)) + 3) & ~3;
   return (size_t)goff * 4 + (size_t)KP * 8 + (size_t)KP * 4 * 2;  // G | b | c, d
 }
 
-template <int KP, bool RAGGED, int PREC, bool FORM>
+template <int KP, bool RAGGED, int PREC, bool FORM, int PF>
 static hipError_t gram_launch(const GramArgs& a, int max_blocks, hipStream_t s, int* grid_out) {
-  const size_t lds = gram_lds_bytes(a.K, KP, PREC);
-  auto fn = k_gram<KP, RAGGED, PREC, FORM>;
+  const size_t lds = gram_lds_bytes(a.K, KP, PREC, PF);
+  auto fn = k_gram<KP, RAGGED, PREC, FORM, PF>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -742,41 +750,45 @@ static hipError_t gram_launch(const GramArgs& a, int max_blocks, hipStream_t s, 
   return hipGetLastError();
 }
 
-template <bool RAGGED, int PREC, bool FORM>
+template <bool RAGGED, int PREC, bool FORM, int PF>
 static hipError_t gram_kp(int kp, const GramArgs& a, int max_blocks, hipStream_t s, int* g) {
   if constexpr (FORM) {  // K <= 128: G formed here, iterated by k_gram_iter
     switch (kp) {
-      case 32: return gram_launch<32, RAGGED, PREC, true>(a, max_blocks, s, g);
-      case 64: return gram_launch<64, RAGGED, PREC, true>(a, max_blocks, s, g);
-      case 96: return gram_launch<96, RAGGED, PREC, true>(a, max_blocks, s, g);
-      case 128: return gram_launch<128, RAGGED, PREC, true>(a, max_blocks, s, g);
+      case 32: return gram_launch<32, RAGGED, PREC, true, PF>(a, max_blocks, s, g);
+      case 64: return gram_launch<64, RAGGED, PREC, true, PF>(a, max_blocks, s, g);
+      case 96: return gram_launch<96, RAGGED, PREC, true, PF>(a, max_blocks, s, g);
+      case 128: return gram_launch<128, RAGGED, PREC, true, PF>(a, max_blocks, s, g);
       default: break;
     }
   } else {
     switch (kp) {
-      case 160: return gram_launch<160, RAGGED, PREC, false>(a, max_blocks, s, g);
-      case 192: return gram_launch<192, RAGGED, PREC, false>(a, max_blocks, s, g);
-      case 224: return gram_launch<224, RAGGED, PREC, false>(a, max_blocks, s, g);
+      case 160: return gram_launch<160, RAGGED, PREC, false, PF>(a, max_blocks, s, g);
+      case 192: return gram_launch<192, RAGGED, PREC, false, PF>(a, max_blocks, s, g);
+      case 224: return gram_launch<224, RAGGED, PREC, false, PF>(a, max_blocks, s, g);
       default: break;
     }
   }
   return hipErrorInvalidValue;
 }
 
-template <bool FORM>
+template <bool FORM, int PF>
 static hipError_t gram_form(int kp, bool ragged, const GramArgs& a, int max_blocks, hipStream_t s,
                             int* grid_out) {
   if (a.prec == PREC_BF16X3)
-    return ragged ? gram_kp<true, PREC_BF16X3, FORM>(kp, a, max_blocks, s, grid_out)
-                  : gram_kp<false, PREC_BF16X3, FORM>(kp, a, max_blocks, s, grid_out);
-  return ragged ? gram_kp<true, PREC_FP32, FORM>(kp, a, max_blocks, s, grid_out)
-                : gram_kp<false, PREC_FP32, FORM>(kp, a, max_blocks, s, grid_out);
+    return ragged ? gram_kp<true, PREC_BF16X3, FORM, PF>(kp, a, max_blocks, s, grid_out)
+                  : gram_kp<false, PREC_BF16X3, FORM, PF>(kp, a, max_blocks, s, grid_out);
+  return ragged ? gram_kp<true, PREC_FP32, FORM, PF>(kp, a, max_blocks, s, grid_out)
+                : gram_kp<false, PREC_FP32, FORM, PF>(kp, a, max_blocks, s, grid_out);
 }
 
 hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, hipStream_t s,
                        int* grid_out, bool form) {
-  return form ? gram_form<true>(kp, ragged, a, max_blocks, s, grid_out)
-              : gram_form<false>(kp, ragged, a, max_blocks, s, grid_out);
+  if (a.ahead != 1 && a.ahead != 2) return hipErrorInvalidValue;
+  if (a.ahead == 1)
+    return form ? gram_form<true, 1>(kp, ragged, a, max_blocks, s, grid_out)
+                : gram_form<false, 1>(kp, ragged, a, max_blocks, s, grid_out);
+  return form ? gram_form<true, 2>(kp, ragged, a, max_blocks, s, grid_out)
+              : gram_form<false, 2>(kp, ragged, a, max_blocks, s, grid_out);
 }
 
 // ---------------------------------------------------------------------------

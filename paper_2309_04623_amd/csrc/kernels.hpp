@@ -226,8 +226,9 @@ struct GramArgs {
   double* bf;
   float* cf;
   int* visits;  // nullable: per frame, incremented each time a workgroup takes it
+  int ahead;    // chunks of pixel rows gathered ahead of their first use: 1 or 2
 };
-size_t gram_lds_bytes(int K, int KP, int prec);
+size_t gram_lds_bytes(int K, int KP, int prec, int ahead);
 // form = true (required for KP <= 128, refused above): the launch only
 // forms G, b and the start of every frame (Gf, bf, cf; warm-start decision
 // included); launch_gram_iter then runs the iterations, one frame per

@@ -360,3 +360,34 @@ def test_stop_rule_warm_start_restart_and_fallback():
     assert rep["status_flags"] & (1 << nmf.NMF_WARN_MAXITER)  # frames 0..7 never met it
     assert np.all(its[8:] <= 2 * ce)
     _compare(T[:8], MT[:8], H, host(C)[:8], Co[:8])
+
+
+@pytest.mark.parametrize("k,precision", [(100, "bf16x3"), (30, "fp32"), (200, "bf16x3"), (170, "fp32")])
+def test_autotuned_gather_depth_gives_the_same_bits(k, precision):
+    """With NMF_F_AUTOTUNE the gather depth of the persistent launch is timed
+    on the call's own inputs and cached per shape; it changes no arithmetic,
+    so dense and CSR results equal the default launch's bit for bit (first
+    call: tuning runs, second call: cached choice)."""
+    p, f = 1500, 40
+    H = _basis(k, p, seed=k)
+    T, MT = _photon_frames(H, f, seed=k + 1)
+    g = np.random.default_rng(k)
+    offs, pix, val, wt = _ragged(H, g.integers(0, p + 1, f), seed=k + 2, binary=False)
+    h = nmf.Handle(0)
+    say("autotune gram dense", k, precision)
+    Cd, _ = nmf.project(dev(H), dev(T), dev(MT), 40, seed=3, gram=True, precision=precision)
+    Cr, _ = nmf.project_ragged(dev(H), dev_i64(offs), dev_i32(pix), dev(val), dev(wt), 40, seed=3,
+                               precision=precision)
+    for rep in range(2):
+        say("autotune gram", k, precision, rep)
+        Ct, _ = nmf.project(dev(H), dev(T), dev(MT), 40, seed=3, gram=True, precision=precision,
+                            flags=nmf.F_AUTOTUNE, handle=h)
+        assert np.array_equal(host(Ct), host(Cd))
+        Ct, _ = nmf.project_ragged(dev(H), dev_i64(offs), dev_i32(pix), dev(val), dev(wt), 40,
+                                   seed=3, precision=precision, flags=nmf.F_AUTOTUNE, handle=h)
+        assert np.array_equal(host(Ct), host(Cr))
+    report = nmf.autotune_report(h)
+    print(report, flush=True)
+    lines = [l for l in report.splitlines() if l.startswith("gram.")]
+    assert len(lines) == 2 and all("pipeline=1" in l or "pipeline=2" in l for l in lines)
+    h.close()
