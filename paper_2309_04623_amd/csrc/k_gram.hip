@@ -32,6 +32,8 @@
 
 namespace nmf {
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 // One LDS DMA of 16 bytes per lane: lane i's bytes land at lds + 16 i.
 __device__ __forceinline__ void gram_dma16(const void* src, float* lds) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
@@ -119,10 +121,10 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   // b = H (m o t) on groups of KP threads, thread (bgrp, bcomp) summing
   // component bcomp over its group's pixels of each chunk: FP32 form, BG
   // groups of BPX consecutive pixels; split form, SG groups that take every
-  // SG-th pixel pair in the staging pass
+  // SG-th group of eight pixels in the staging pass
   constexpr int BG = NTH / KP >= 8 ? 8 : NTH / KP >= 4 ? 4 : NTH / KP >= 2 ? 2 : 1;
   constexpr int BPX = 32 / BG;
-  constexpr int SG = NTH / KP < 16 ? NTH / KP : 16;
+  constexpr int SG = NTH / KP < 4 ? NTH / KP : 4;
   constexpr int NBG = PREC == PREC_BF16X3 ? SG : BG;
   const int K = a.K;
   // PF: chunks gathered ahead of their first use; LEAD: chunks staged ahead
@@ -352,9 +354,11 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       asm volatile("" ::: "memory");
     };
     // split form: transposed staging of w = h sqrt(m) of one chunk into
-    // buffer wb, thread (bgrp, bcomp) -> component bcomp, pixel pairs bgrp,
-    // bgrp + SG, ...: the reads of Hs are consecutive across threads; the
-    // same pass adds the chunk's b terms
+    // buffer wb, thread (bgrp, bcomp) -> component bcomp, pixels 8 q .. 8 q
+    // + 7 for q = bgrp, bgrp + SG, ... < 4: the reads of Hs are consecutive
+    // across threads, each thread writes its four pixel pairs of hi and of
+    // lo as one 16-byte word (the row stride keeps those conflict-free, as
+    // for the operand reads); the same pass adds the chunk's b terms
     auto stage = [&](const float* Hsrc, int slot, int wb) {
       const float* msl = msr + 32 * slot;
       const float* tsl = tsr + 32 * slot;
@@ -363,16 +367,36 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       uint32_t* dlo = dhi + WB;
       // components K.. are not staged (see gram_staged_rows)
       if (bgrp < SG && bcomp < K) {
-        for (int pp = bgrp; pp < 16; pp += SG) {
-          const float h0 = Hsrc[(2 * pp) * KP + bcomp], h1 = Hsrc[(2 * pp + 1) * KP + bcomp];
-          const f32x2 wv = {h0 * qsl[2 * pp], h1 * qsl[2 * pp + 1]};
-          const bf16x2 wh = __builtin_convertvector(wv, bf16x2);
-          const bf16x2 wl = __builtin_convertvector(wv - __builtin_convertvector(wh, f32x2), bf16x2);
-          const int o = bcomp * GT_STRIDE + pp;
-          dhi[o] = __builtin_bit_cast(uint32_t, wh);
-          dlo[o] = __builtin_bit_cast(uint32_t, wl);
-          bacc += (double)(h0 * msl[2 * pp]) * (double)tsl[2 * pp];
-          bacc += (double)(h1 * msl[2 * pp + 1]) * (double)tsl[2 * pp + 1];
+        for (int q = bgrp; q < 4; q += SG) {
+          float h[8], qv[8], mv[8], tv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) h[u] = Hsrc[(8 * q + u) * KP + bcomp];
+#pragma unroll
+          for (int u4 = 0; u4 < 2; ++u4) {
+            const f32x4 q4 = *reinterpret_cast<const f32x4*>(qsl + 8 * q + 4 * u4);
+            const f32x4 m4 = *reinterpret_cast<const f32x4*>(msl + 8 * q + 4 * u4);
+            const f32x4 t4 = *reinterpret_cast<const f32x4*>(tsl + 8 * q + 4 * u4);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              qv[4 * u4 + u] = q4[u];
+              mv[4 * u4 + u] = m4[u];
+              tv[4 * u4 + u] = t4[u];
+            }
+          }
+          u32x4 hi4, lo4;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const f32x2 wv = {h[2 * v] * qv[2 * v], h[2 * v + 1] * qv[2 * v + 1]};
+            const bf16x2 wh = __builtin_convertvector(wv, bf16x2);
+            const bf16x2 wl = __builtin_convertvector(wv - __builtin_convertvector(wh, f32x2), bf16x2);
+            hi4[v] = __builtin_bit_cast(uint32_t, wh);
+            lo4[v] = __builtin_bit_cast(uint32_t, wl);
+          }
+          const int o = bcomp * GT_STRIDE + 4 * q;
+          *reinterpret_cast<u32x4*>(dhi + o) = hi4;
+          *reinterpret_cast<u32x4*>(dlo + o) = lo4;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) bacc += (double)(h[u] * mv[u]) * (double)tv[u];
         }
       }
     };
