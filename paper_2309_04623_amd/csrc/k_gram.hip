@@ -33,6 +33,7 @@
 namespace nmf {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // One LDS DMA of 16 bytes per lane: lane i's bytes land at lds + 16 i.
 __device__ __forceinline__ void gram_dma16(const void* src, float* lds) {
@@ -90,12 +91,12 @@ constexpr int GT_STRIDE = 20;
 __host__ __device__ constexpr int gram_staged_rows(int K, int KP) { return KP <= 128 ? KP : K; }
 
 // LDS floats of the pixel loop with rows gathered PF chunks ahead of their
-// first use: gathered rows [PF+1][32][KP], rings of pixel indices, weights,
-// data and square-rooted weights [PF+2][32] each, the raw pixel indices,
-// weights and data as fetched [2][3][32], and (bf16x3) two transposed hi/lo
-// pairs [2][2][rows][GT_STRIDE]
+// first use: gathered rows [PF+1][32][KP], rings of pixel indices, weights
+// and square-rooted weights [PF+2][32] each, the raw pixel indices, weights
+// and data as fetched [2][3][32], a ring of the FP64 products m t
+// [PF+2][32], and (bf16x3) two transposed hi/lo pairs [2][2][rows][GT_STRIDE]
 __host__ __device__ constexpr int gram_stage_floats(int K, int KP, int prec, int pf) {
-  return 32 * (pf + 1) * KP + 128 * (pf + 2) + 192 +
+  return 32 * (pf + 1) * KP + 96 * (pf + 2) + 192 + 64 * (pf + 2) +
          (prec == PREC_BF16X3 ? 4 * gram_staged_rows(K, KP) * GT_STRIDE : 0);
 }
 
@@ -136,17 +137,18 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   constexpr int NH = PF + 1, NM = GA + 2 - LEAD;
   // [NH][32][KP] gathered H^T rows (the chunk in use and the next PF)
   float* Hsb = lds;
-  // rings of NM chunks' pixel indices, weights, data and square roots of
-  // the weights ([NM][32] each)
+  // rings of NM chunks' pixel indices, weights and square roots of the
+  // weights ([NM][32] each)
   int* pixr = reinterpret_cast<int*>(lds + 32 * NH * KP);
   float* msr = lds + 32 * NH * KP + 32 * NM;
-  float* tsr = msr + 32 * NM;
-  float* qsr = tsr + 32 * NM;
+  float* qsr = msr + 32 * NM;
   // two chunks' raw pixel indices, weights and data, as fetched ([2][3][32])
   float* rawr = qsr + 32 * NM;
+  // ring of the pixels' m t in FP64 (exact products of the two floats)
+  double* mtr = reinterpret_cast<double*>(rawr + 192);
   // two buffers of bf16 hi/lo of (H o sqrt m)^T, [2][2][rows][GT_STRIDE]
   // dwords (2 pixels each)
-  uint32_t* wT = reinterpret_cast<uint32_t*>(rawr + 192);
+  uint32_t* wT = reinterpret_cast<uint32_t*>(mtr + 32 * NM);
   const int WB = gram_staged_rows(K, KP) * GT_STRIDE;  // dwords of one hi or lo array
   float* G = lds;             // [K][K] after the pixel loop (aliases the above)
   const int goff = (max(K * K, gram_stage_floats(K, KP, PREC, PF)) + 3) & ~3;
@@ -330,8 +332,8 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       }
       pixr[32 * slot + tid] = prow;
       msr[32 * slot + tid] = m;
-      tsr[32 * slot + tid] = t;
       qsr[32 * slot + tid] = sqrtf(m);
+      mtr[32 * slot + tid] = (double)m * (double)t;
     };
     auto gather = [&](int slot, float* dst) {  // all waves: 32 rows of H^T
 #pragma unroll
@@ -360,28 +362,28 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
     // lo as one 16-byte word (the row stride keeps those conflict-free, as
     // for the operand reads); the same pass adds the chunk's b terms
     auto stage = [&](const float* Hsrc, int slot, int wb) {
-      const float* msl = msr + 32 * slot;
-      const float* tsl = tsr + 32 * slot;
       const float* qsl = qsr + 32 * slot;
+      const double* mtl = mtr + 32 * slot;
       uint32_t* dhi = wT + wb * 2 * WB;
       uint32_t* dlo = dhi + WB;
       // components K.. are not staged (see gram_staged_rows)
       if (bgrp < SG && bcomp < K) {
         for (int q = bgrp; q < 4; q += SG) {
-          float h[8], qv[8], mv[8], tv[8];
+          float h[8], qv[8];
+          double mt[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) h[u] = Hsrc[(8 * q + u) * KP + bcomp];
 #pragma unroll
           for (int u4 = 0; u4 < 2; ++u4) {
             const f32x4 q4 = *reinterpret_cast<const f32x4*>(qsl + 8 * q + 4 * u4);
-            const f32x4 m4 = *reinterpret_cast<const f32x4*>(msl + 8 * q + 4 * u4);
-            const f32x4 t4 = *reinterpret_cast<const f32x4*>(tsl + 8 * q + 4 * u4);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              qv[4 * u4 + u] = q4[u];
-              mv[4 * u4 + u] = m4[u];
-              tv[4 * u4 + u] = t4[u];
-            }
+            for (int u = 0; u < 4; ++u) qv[4 * u4 + u] = q4[u];
+          }
+#pragma unroll
+          for (int u2 = 0; u2 < 4; ++u2) {
+            const f64x2 m2 = *reinterpret_cast<const f64x2*>(mtl + 8 * q + 2 * u2);
+            mt[2 * u2] = m2[0];
+            mt[2 * u2 + 1] = m2[1];
           }
           u32x4 hi4, lo4;
 #pragma unroll
@@ -396,7 +398,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
           *reinterpret_cast<u32x4*>(dhi + o) = hi4;
           *reinterpret_cast<u32x4*>(dlo + o) = lo4;
 #pragma unroll
-          for (int u = 0; u < 8; ++u) bacc += (double)(h[u] * mv[u]) * (double)tv[u];
+          for (int u = 0; u < 8; ++u) bacc = fma((double)h[u], mt[u], bacc);
         }
       }
     };
@@ -424,7 +426,6 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       const int sl = c % NM;
       const float* Hs = Hsb + (c % NH) * 32 * KP;
       const float* ms = msr + 32 * sl;
-      const float* ts = tsr + 32 * sl;
       // chunk c + GA + 2's pixel data (before the gather: older DMAs land
       // first)
       if (tid < 32 && base + 32 * (GA + 2) < e) meta_fetch((c + GA) & 1, base + 32 * (GA + 2));
@@ -505,7 +506,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
 #pragma unroll
           for (int u = 0; u < BPX; ++u) {
             const int jr = bgrp * BPX + u;
-            bacc += (double)(Hs[jr * KP + bcomp] * ms[jr]) * (double)ts[jr];
+            bacc = fma((double)Hs[jr * KP + bcomp], mtr[32 * sl + jr], bacc);
           }
         }
       }
