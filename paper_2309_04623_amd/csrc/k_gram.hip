@@ -72,8 +72,9 @@ __host__ __device__ constexpr int gram_waves() {
 //     w < 2, (p,r); three waves for NB = 3;
 //   2 (7 blocks, eight waves): wave w < 7 takes the blocks of the line
 //     {w, w + 1, w + 3} (mod 7) of the Fano plane, whose seven lines hold
-//     every pair of blocks exactly once, and the tiles (w,w), (w,w+1),
-//     (w,w+3), (w+1,w+3);
+//     every pair of blocks exactly once, and the tiles (w,w+1), (w,w+3),
+//     (w+1,w+3) and, for w < 4, (w,w); wave 7 takes the blocks 4, 5, 6 and
+//     their diagonal tiles, so each SIMD (waves w and w + 4) has seven;
 //   0: tile t to wave t mod NWV, each tile reading both its operands.
 template <int KP, int PREC>
 __host__ __device__ constexpr int gram_pattern() {
@@ -160,6 +161,8 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
   const int bgrp = tid / KP, bcomp = tid - bgrp * KP;
   int tmi[TPW], tmj[TPW];
   int blk[3] = {0, 0, 0};  // the wave's blocks (patterns 1 and 2)
+  int bused = 0;           // which of them its tiles read
+  bool diag3 = false;      // pattern 2, wave 7: the tiles (4,4), (5,5), (6,6)
   if constexpr (GP == 0) {
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
@@ -181,16 +184,30 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       blk[2] = (wave + 2) % NB;
       ntl = NB == 4 ? (wave < 2 ? 3 : 2) : (wave < 3 ? 2 : 0);
     } else {
-      blk[0] = wave;
-      blk[1] = (wave + 1) % 7;
-      blk[2] = (wave + 3) % 7;
+      blk[0] = wave < 7 ? wave : 4;
+      blk[1] = wave < 7 ? (wave + 1) % 7 : 5;
+      blk[2] = wave < 7 ? (wave + 3) % 7 : 6;
       ntl = wave < 7 ? 4 : 0;
+      diag3 = wave == 7;
     }
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
       tmi[q] = q < ntl ? blk[LA[q]] : -1;
       tmj[q] = q < ntl ? blk[LB[q]] : -1;
     }
+    if constexpr (GP == 2) {
+      // waves 4-6 leave their diagonal tile to wave 7, which has no line:
+      // seven tiles per SIMD (waves w and w + 4 share one)
+      if (wave >= 4 && wave < 7) tmi[0] = tmj[0] = -1;
+      if (diag3) {
+        tmi[0] = tmj[0] = 4;
+        tmi[1] = tmj[1] = 5;
+        tmi[2] = tmj[2] = 6;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < TPW; ++q)
+      if (tmi[q] >= 0) bused |= diag3 ? 1 << q : (1 << LA[q]) | (1 << LB[q]);
   }
   const uint64_t key = sm_key(a.seed, 2);
   int bad = 0;
@@ -444,16 +461,20 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
             bf16x8 bh[3], bl[3];
 #pragma unroll
             for (int l = 0; l < 3; ++l) {
-              // block 0 serves every tile, block l > 0 the tiles of slot l on
-              const bool used = l == 0 ? tmi[0] >= 0 : (l < TPW && tmj[l] >= 0);
+              const bool used = (bused >> l) & 1;
               const int r = (32 * blk[l] + col) * GT_STRIDE + d;
               bh[l] = used ? *reinterpret_cast<const bf16x8*>(whi + r) : bf16x8{};
               bl[l] = used ? *reinterpret_cast<const bf16x8*>(wlo + r) : bf16x8{};
             }
+            if (GP == 2 && diag3) {
 #pragma unroll
-            for (int q = 0; q < TPW; ++q)
-              if (tmi[q] >= 0)
-                acc[q] = mfma_bf16x3(bh[LA[q]], bl[LA[q]], bh[LB[q]], bl[LB[q]], acc[q]);
+              for (int q = 0; q < 3; ++q) acc[q] = mfma_bf16x3(bh[q], bl[q], bh[q], bl[q], acc[q]);
+            } else {
+#pragma unroll
+              for (int q = 0; q < TPW; ++q)
+                if (tmi[q] >= 0)
+                  acc[q] = mfma_bf16x3(bh[LA[q]], bl[LA[q]], bh[LB[q]], bl[LB[q]], acc[q]);
+            }
           }
           return;
         }
