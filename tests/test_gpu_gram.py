@@ -215,21 +215,29 @@ def test_cfg4_batch_256_sampled_frames(precision):
     assert np.all(t[:, 0] > 0) and np.all(t[:, 1] >= t[:, 0])
 
 
-@pytest.mark.parametrize("k,p,sizes", [(30, 6400, [6400, 0, 3000, 31, 32, 33, 5000]),
-                                       (100, 3000, [2999, 1500, 64, 700]),
-                                       (200, 2500, [2500, 1200, 300])])
-def test_ragged_bf16x3_parity(k, p, sizes):
-    """Split-precision Gram products on CSR frames: model within 1e-4, the
-    objective within the bar derived from the split form's product error
-    (frames of about K pixels are fitted almost exactly, so their objective
-    is a small difference that a model change moves a lot)."""
+@pytest.mark.parametrize("k,p,sizes,binary", [(30, 6400, [6400, 0, 3000, 31, 32, 33, 5000], True),
+                                              (100, 3000, [2999, 1500, 64, 700], True),
+                                              (200, 2500, [2500, 1200, 300], True),
+                                              (64, 2100, [2100, 1000, 65], False),
+                                              (80, 2000, [2000, 900, 81, 40], False),
+                                              (100, 3000, [2999, 1500, 64, 700], False),
+                                              (150, 2000, [1999, 1000, 151], True),
+                                              (180, 2200, [2200, 700, 5], False),
+                                              (197, 2500, [2500, 1200, 300], False)])
+def test_ragged_bf16x3_parity(k, p, sizes, binary):
+    """Split-precision Gram products on CSR frames, every operand-block
+    grouping of the staged (H o sqrt m) array and both launch forms, 0/1 and
+    inverse-variance weights: model within 1e-4, the objective within the
+    bar derived from the split form's product error (frames of about K
+    pixels are fitted almost exactly, so their objective is a small
+    difference that a model change moves a lot)."""
     H = _basis(k, p, seed=k + 1)
-    offs, pix, val, wt = _ragged(H, sizes, seed=k, binary=True)
+    offs, pix, val, wt = _ragged(H, sizes, seed=k, binary=binary)
     f = len(sizes)
     C0 = prng.init_matrix(9, prng.MAT_C, f, k)
-    say("ragged bf16x3", k, p, sizes)
-    C, _ = nmf.project_ragged(dev(H), dev_i64(offs), dev_i32(pix), dev(val), None, 100, seed=9,
-                              precision="bf16x3")
+    say("ragged bf16x3", k, p, sizes, binary)
+    C, _ = nmf.project_ragged(dev(H), dev_i64(offs), dev_i32(pix), dev(val),
+                              None if binary else dev(wt), 100, seed=9, precision="bf16x3")
     Cg = host(C)
     Co = nmf64.project_ragged(offs, pix, val, wt, H, C0, 100)
     T, MT = nmf64.ragged_to_dense(offs, pix, val, wt, p)
