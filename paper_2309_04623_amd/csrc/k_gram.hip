@@ -635,11 +635,12 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
     }
 
     if constexpr (!FORM) {
-      // ---- iterations (K > 128): (c G)_j with G read from LDS -------------
-      // Two threads, j and j + 256, share row j of the product: each sums half
-      // of the components (consecutive j across lanes read consecutive words,
-      // conflict-free), the upper one leaves its sum in LDS for the lower one,
-      // which owns coefficient j.  Optional per-frame stop rule: every
+      // ---- iterations (K > 128): (c G)_j, half a row of G per thread -----
+      // Two threads, j and j + 256, share row j of the product: each keeps
+      // KP/2 entries of row j of G (G is symmetric: row j is column j) in
+      // registers and sums that half of the components, the upper one
+      // leaves its sum in LDS for the lower one, which owns coefficient j.
+      // Optional per-frame stop rule: every
       // check_every iterations the model change since the previous check,
       // d = c - c_prev, is tested against the model, d G d^T <= tol^2 c G c^T
       // (both in FP64; c G is the denominator just formed, d G one more
@@ -655,45 +656,25 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       const f32x4* d4 = reinterpret_cast<const f32x4*>(dsh);
       const int ce = a.check_every;
       __shared__ int run_sh[2];  // iterations run, rule met
-      const float* gcol = G + (j < K ? j : 0);
-      // quads of components: the lower half takes [0, h4), the upper [h4, K/4)
-      // and the last K % 4; each index i goes into partial sum i % 4
-      const int K4 = K >> 2, kr = K & 3, h4 = (K4 + 1) >> 1;
-      const int qa = hf ? h4 : 0, qb = hf ? K4 : h4;
-      auto matvec_part = [&](const float* v, const f32x4* v4) -> float {
-        float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
-        if (j < K) {
-          int i4 = qa;
-          // eight column entries per step, all read before they are used
-          for (; i4 + 2 <= qb; i4 += 2) {
-            const f32x4 ca = v4[i4], cb = v4[i4 + 1];
-            const float* gc = gcol + 4 * i4 * K;
-            float gv[8];
+      // thread (j, hf) holds G[j][hf KH + i], i < KH (zero past K); each
+      // index i goes into partial sum i % 4
+      constexpr int KH = KP / 2;
+      float g[KH];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) gv[u] = gc[u * K];
-            d0 = fmaf(ca[0], gv[0], d0);
-            d1 = fmaf(ca[1], gv[1], d1);
-            d2 = fmaf(ca[2], gv[2], d2);
-            d3 = fmaf(ca[3], gv[3], d3);
-            d0 = fmaf(cb[0], gv[4], d0);
-            d1 = fmaf(cb[1], gv[5], d1);
-            d2 = fmaf(cb[2], gv[6], d2);
-            d3 = fmaf(cb[3], gv[7], d3);
-          }
-          if (i4 < qb) {
-            const f32x4 cv = v4[i4];
-            const float* gc = gcol + 4 * i4 * K;
-            d0 = fmaf(cv[0], gc[0], d0);
-            d1 = fmaf(cv[1], gc[K], d1);
-            d2 = fmaf(cv[2], gc[2 * K], d2);
-            d3 = fmaf(cv[3], gc[3 * K], d3);
-          }
-          if (hf) {
-            const float* gc = gcol + 4 * K4 * K;
-            if (kr > 0) d0 = fmaf(v[4 * K4], gc[0], d0);
-            if (kr > 1) d1 = fmaf(v[4 * K4 + 1], gc[K], d1);
-            if (kr > 2) d2 = fmaf(v[4 * K4 + 2], gc[2 * K], d2);
-          }
+      for (int i = 0; i < KH; ++i) {
+        const int col = hf * KH + i;
+        g[i] = (j < K && col < K) ? G[j * K + col] : 0.f;
+      }
+      auto matvec_part = [&](const float* v, const f32x4* v4) -> float {
+        (void)v;
+        float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+#pragma unroll
+        for (int i4 = 0; i4 < KH / 4; ++i4) {
+          const f32x4 cv = v4[hf * (KH / 4) + i4];
+          d0 = fmaf(cv[0], g[4 * i4 + 0], d0);
+          d1 = fmaf(cv[1], g[4 * i4 + 1], d1);
+          d2 = fmaf(cv[2], g[4 * i4 + 2], d2);
+          d3 = fmaf(cv[3], g[4 * i4 + 3], d3);
         }
         return (d0 + d1) + (d2 + d3);
       };
