@@ -265,10 +265,15 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
     // used two chunks later, stay in flight).  A pixel outside the frame or
     // with an invalid index gathers row 0 (finite) under weight 0, so it
     // adds exactly nothing.
+    // The pixel data of a chunk are fetched and checked by lanes 0-31 of the
+    // last wave (the meta lanes), the wave with the fewest tiles and no
+    // staging share at K > 128.
+    const bool mw = wave == NWV - 1 && lane < 32;
+    const int ml = lane;
     int mp = 0;
     float mm = 0.f, mt = 0.f;
-    auto meta_load = [&](int64_t b0) {  // threads < 32: chunk at b0
-      const int64_t jj = b0 + tid;
+    auto meta_load = [&](int64_t b0) {  // meta lanes: chunk at b0
+      const int64_t jj = b0 + ml;
       mp = -1;
       mm = 0.f;
       mt = 0.f;
@@ -284,8 +289,8 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
         }
       }
     };
-    auto meta_fetch = [&](int rs, int64_t b0) {  // threads < 32: chunk at b0, by DMA
-      const int64_t jj = min(b0 + tid, e - 1);  // lanes past the frame: any valid entry
+    auto meta_fetch = [&](int rs, int64_t b0) {  // meta lanes: chunk at b0, by DMA
+      const int64_t jj = min(b0 + ml, e - 1);  // lanes past the frame: any valid entry
       float* rw = rawr + 96 * rs;
       if constexpr (RAGGED) {
         gram_dma4(a.pix + jj, rw);
@@ -296,25 +301,25 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
         gram_dma4(a.T + (int64_t)f * a.P + jj, rw + 64);
       }
     };
-    auto meta_take = [&](int rs, int64_t b0) {  // threads < 32: fetched values
-      const int64_t jj = b0 + tid;
+    auto meta_take = [&](int rs, int64_t b0) {  // meta lanes: fetched values
+      const int64_t jj = b0 + ml;
       const float* rw = rawr + 96 * rs;
       mp = -1;
       mm = 0.f;
       mt = 0.f;
       if (jj < e) {
         if constexpr (RAGGED) {
-          mp = __builtin_bit_cast(int, rw[tid]);
-          mm = a.wt ? rw[32 + tid] : 1.0f;
+          mp = __builtin_bit_cast(int, rw[ml]);
+          mm = a.wt ? rw[32 + ml] : 1.0f;
         } else {
           mp = (int)jj;
-          mm = rw[32 + tid];
+          mm = rw[32 + ml];
         }
-        mt = rw[64 + tid];
+        mt = rw[64 + ml];
       }
     };
-    auto meta_store = [&](int slot, int64_t b0) {  // threads < 32: validated
-      const int64_t jj = b0 + tid;
+    auto meta_store = [&](int slot, int64_t b0) {  // meta lanes: validated
+      const int64_t jj = b0 + ml;
       float m = 0.f, t = 0.f;
       int prow = 0;
       if (jj < e) {
@@ -347,10 +352,10 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
           t = 0.f;
         }
       }
-      pixr[32 * slot + tid] = prow;
-      msr[32 * slot + tid] = m;
-      qsr[32 * slot + tid] = sqrtf(m);
-      mtr[32 * slot + tid] = (double)m * (double)t;
+      pixr[32 * slot + ml] = prow;
+      msr[32 * slot + ml] = m;
+      qsr[32 * slot + ml] = sqrtf(m);
+      mtr[32 * slot + ml] = (double)m * (double)t;
     };
     auto gather = [&](int slot, float* dst) {  // all waves: 32 rows of H^T
 #pragma unroll
@@ -420,7 +425,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       }
     };
     if (s < e) {
-      if (tid < 32) {
+      if (mw) {
 #pragma unroll
         for (int x = 0; x <= GA; ++x) {
           meta_load(s + 32 * x);
@@ -445,7 +450,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
       const float* ms = msr + 32 * sl;
       // chunk c + GA + 2's pixel data (before the gather: older DMAs land
       // first)
-      if (tid < 32 && base + 32 * (GA + 2) < e) meta_fetch((c + GA) & 1, base + 32 * (GA + 2));
+      if (mw && base + 32 * (GA + 2) < e) meta_fetch((c + GA) & 1, base + 32 * (GA + 2));
       const bool ahead = base + 32 * GA < e;
       if (ahead) gather((c + GA) % NM, Hsb + ((c + GA) % NH) * 32 * KP);
 
@@ -537,7 +542,7 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
         nfold = 0;
         fold();
       }
-      if (tid < 32) {
+      if (mw) {
         meta_take((c + GA + 1) & 1, base + 32 * (GA + 1));
         meta_store((c + GA + 1) % NM, base + 32 * (GA + 1));
       }
