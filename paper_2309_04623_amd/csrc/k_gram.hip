@@ -825,32 +825,45 @@ hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, h
 
 // ---------------------------------------------------------------------------
 // Iterations of the two-phase form (K <= 128): one frame per workgroup of
-// one wave (KP <= 64) or two.  Thread j keeps row j of the frame's G in
-// registers and updates coefficient j; the coefficients travel through a
-// double buffer in LDS, so one barrier per iteration suffices (iteration t
-// reads buffer t % 2 and writes the other).  The update and the stop rule
-// are those of the one-launch form of k_gram for larger K (FP64 ratio and
-// objective sums, four FP32 partial sums per row product).
+// KR / 32 waves rounded up.  Lanes l and l + 32 of wave w share row
+// j = 32 w + l of the product: each keeps half of row j of the frame's G in
+// registers (KR / 2 entries; G is symmetric, so row j is column j), the two
+// half sums meet through a lane exchange and are added in the same order in
+// both lanes, and lane l updates coefficient j.  The coefficients travel
+// through a double buffer in LDS, so one barrier per iteration suffices
+// (iteration t reads buffer t % 2 and writes the other).  The update and the
+// stop rule are those of the one-launch form of k_gram for larger K (FP64
+// ratio and objective sums, four FP32 partial sums per half row).
 // ---------------------------------------------------------------------------
+template <int KR>
+__host__ __device__ constexpr int gram_iter_threads() {
+  return 64 * ((KR + 31) / 32);
+}
+
 template <int KP, int KR>
-__global__ __launch_bounds__(KP <= 64 ? 64 : 128) void k_gram_iter(GramArgs a) {
+__global__ __launch_bounds__(gram_iter_threads<KR>()) void k_gram_iter(GramArgs a) {
   static_assert(KR % 8 == 0 && KR <= KP, "row length: K rounded up to 8");
-  constexpr int NT = KP <= 64 ? 64 : 128;
+  constexpr int NT = gram_iter_threads<KR>();
   constexpr int NW = NT / 64;
-  constexpr int KQ = KR / 4;  // the products with the zero padding of G are left out
+  constexpr int KH = KR / 2;  // entries of a half row (the zero padding past KR left out)
   __shared__ __align__(16) float cb[2][KP];
   __shared__ __align__(16) float dsh[KP];
   __shared__ double wsel[2][NW];
   const int f = blockIdx.x;
   if (f >= a.F) return;
   const int K = a.K;
-  const int j = threadIdx.x, wave = j >> 6, lane = j & 63;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int j = 32 * wave + (lane & 31), hf = lane >> 5;
+  const bool own = hf == 0 && j < K;  // lane that writes coefficient j
   const uint64_t key = sm_key(a.seed, 2);
-  float g[KR];
+  float g[KH];
   const float* Gr = a.Gf + (int64_t)f * K * K + (j < K ? j : 0) * K;
 #pragma unroll
-  for (int i = 0; i < KR; ++i) g[i] = (j < K && i < K) ? Gr[i] : 0.f;
-  const double bj = j < KP ? a.bf[(int64_t)f * KP + j] : 0.0;
+  for (int i = 0; i < KH; ++i) {
+    const int col = hf * KH + i;
+    g[i] = (j < K && col < K) ? Gr[col] : 0.f;
+  }
+  const double bj = j < K ? a.bf[(int64_t)f * KP + j] : 0.0;
   const bool warm_kept = a.warm && a.fallback && a.fallback[f] == 0;
   const int ce = a.check_every;
   auto sync = [&]() {
@@ -862,18 +875,21 @@ __global__ __launch_bounds__(KP <= 64 ? 64 : 128) void k_gram_iter(GramArgs a) {
       __syncthreads();
     }
   };
+  // (v G)_j, the same value in both lanes of row j
   auto matvec = [&](const float* v) -> float {
-    const f32x4* v4 = reinterpret_cast<const f32x4*>(v);
+    const f32x4* v4 = reinterpret_cast<const f32x4*>(v) + hf * (KH / 4);
     float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
 #pragma unroll
-    for (int i4 = 0; i4 < KQ; ++i4) {
+    for (int i4 = 0; i4 < KH / 4; ++i4) {
       const f32x4 cv = v4[i4];
       d0 = fmaf(cv[0], g[4 * i4 + 0], d0);
       d1 = fmaf(cv[1], g[4 * i4 + 1], d1);
       d2 = fmaf(cv[2], g[4 * i4 + 2], d2);
       d3 = fmaf(cv[3], g[4 * i4 + 3], d3);
     }
-    return (d0 + d1) + (d2 + d3);
+    const float part = (d0 + d1) + (d2 + d3);
+    const float other = __shfl_xor(part, 32);
+    return hf ? other + part : part + other;
   };
   // a sum over all coefficients, the same value in every thread: per wave
   // in a fixed order, then the waves in order
@@ -907,9 +923,9 @@ __global__ __launch_bounds__(KP <= 64 ? 64 : 128) void k_gram_iter(GramArgs a) {
       // the warm start missed the rule by the cap: cold start, same cap
       if (!(warm_kept && ce > 0 && !met)) break;
       cj = j < K ? sm_uniform(key, (uint64_t)f * K + j) : 0.f;
-      if (j == 0) a.fallback[f] = 2;
+      if (tid == 0) a.fallback[f] = 2;
     }
-    if (j < KP) cb[0][j] = cj;
+    if (hf == 0 && j < KP) cb[0][j] = cj;
     sync();
     float cp = cj;
     int it = 0;
@@ -919,12 +935,12 @@ __global__ __launch_bounds__(KP <= 64 ? 64 : 128) void k_gram_iter(GramArgs a) {
       const float den = matvec(cur);
       if (ce > 0 && it > 0 && it % ce == 0) {
         const float dj = j < K ? cj - cp : 0.f;
-        if (j < KP) dsh[j] = dj;
+        if (hf == 0 && j < KP) dsh[j] = dj;
         sync();
         const float dg = matvec(dsh);
         double s1, s2;
-        block_sum2(j < K ? (double)dj * (double)dg : 0.0, j < K ? (double)cj * (double)den : 0.0,
-                   s1, s2);
+        block_sum2(own ? (double)dj * (double)dg : 0.0, own ? (double)cj * (double)den : 0.0, s1,
+                   s2);
         if (s1 <= a.tol2 * s2) {  // the same value in every thread
           stop = true;
           break;
@@ -932,20 +948,20 @@ __global__ __launch_bounds__(KP <= 64 ? 64 : 128) void k_gram_iter(GramArgs a) {
         cp = cj;
       }
       if (j < K) cj = mu_apply_d(cj, bj, (double)den, a.eps);
-      if (j < KP) cb[(it + 1) & 1][j] = cj;
+      if (hf == 0 && j < KP) cb[(it + 1) & 1][j] = cj;
       sync();
     }
     its_total += it;
     met = stop;
   }
-  if (a.iters_out && j == 0) a.iters_out[f] = its_total;
-  if (j < K) a.C_out[(int64_t)f * K + j] = cj;
-  if (a.ticks && j == 0) a.ticks[2 * (int64_t)f + 1] = wall_clock64();
+  if (a.iters_out && tid == 0) a.iters_out[f] = its_total;
+  if (own) a.C_out[(int64_t)f * K + j] = cj;
+  if (a.ticks && tid == 0) a.ticks[2 * (int64_t)f + 1] = wall_clock64();
 }
 
 template <int KP, int KR>
 static void gram_iter_go(const GramArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_gram_iter<KP, KR>), dim3(a.F), dim3(KP <= 64 ? 64 : 128), 0, s, a);
+  hipLaunchKernelGGL((k_gram_iter<KP, KR>), dim3(a.F), dim3(gram_iter_threads<KR>()), 0, s, a);
 }
 
 // The products of a row with G run over K rounded up to 8 (the rest of a

@@ -186,7 +186,10 @@ def test_warm_start_gain_over_cold_start():
         print(f"  median <= {tol:.0e}: cold after {nc} iterations, warm after {nw}", flush=True)
     for a in range(3):
         assert med["warm"][a] <= 0.85 * med["cold"][a]
-    assert all(w <= c for w, c in zip(med["warm"], med["cold"]))
+    # once both starts have reached the FP32 rounding floor of the iterate
+    # (~2e-6 here) the order of the two medians is decided by rounding, not
+    # by the start: compared while the cold error is ten times above it
+    assert all(w <= c for w, c in zip(med["warm"], med["cold"]) if c > 2e-5)
 
 
 def test_warm_start_falls_back_to_cold():
