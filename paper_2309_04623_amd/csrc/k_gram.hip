@@ -828,8 +828,8 @@ hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, h
 // KR / 32 waves rounded up.  Lanes l and l + 32 of wave w share row
 // j = 32 w + l of the product: each keeps half of row j of the frame's G in
 // registers (KR / 2 entries; G is symmetric, so row j is column j), the two
-// half sums meet through a lane exchange and are added in the same order in
-// both lanes, and lane l updates coefficient j.  The coefficients travel
+// half sums meet through a lane swap (v_permlane32_swap, no LDS) and are
+// added in the same order in both lanes, and lane l updates coefficient j.  The coefficients travel
 // through a double buffer in LDS, so one barrier per iteration suffices
 // (iteration t reads buffer t % 2 and writes the other).  The update and the
 // stop rule are those of the one-launch form of k_gram for larger K (FP64
@@ -887,9 +887,11 @@ __global__ __launch_bounds__(gram_iter_threads<KR>()) void k_gram_iter(GramArgs 
       d2 = fmaf(cv[2], g[4 * i4 + 2], d2);
       d3 = fmaf(cv[3], g[4 * i4 + 3], d3);
     }
-    const float part = (d0 + d1) + (d2 + d3);
-    const float other = __shfl_xor(part, 32);
-    return hf ? other + part : part + other;
+    // v_permlane32_swap of the value with itself: element 0 holds the
+    // lower lane's value of the pair (l mod 32), element 1 the upper's
+    const uint32_t pb = __builtin_bit_cast(uint32_t, (d0 + d1) + (d2 + d3));
+    const auto pr = __builtin_amdgcn_permlane32_swap(pb, pb, false, false);
+    return __builtin_bit_cast(float, (uint32_t)pr[0]) + __builtin_bit_cast(float, (uint32_t)pr[1]);
   };
   // a sum over all coefficients, the same value in every thread: per wave
   // in a fixed order, then the waves in order
@@ -928,12 +930,13 @@ __global__ __launch_bounds__(gram_iter_threads<KR>()) void k_gram_iter(GramArgs 
     if (hf == 0 && j < KP) cb[0][j] = cj;
     sync();
     float cp = cj;
-    int it = 0;
+    int it = 0, next_check = ce > 0 ? ce : -1;  // iteration of the next stop-rule check
     bool stop = false;
     for (; it < a.iters; ++it) {
       const float* cur = cb[it & 1];
       const float den = matvec(cur);
-      if (ce > 0 && it > 0 && it % ce == 0) {
+      if (it == next_check) {
+        next_check += ce;
         const float dj = j < K ? cj - cp : 0.f;
         if (hf == 0 && j < KP) dsh[j] = dj;
         sync();
