@@ -695,14 +695,15 @@ __global__ __launch_bounds__(64 * gram_waves<KP>()) void k_gram(GramArgs a) {
           __syncthreads();
         }
         float cj = own ? csh[j] : 0.f, cp = cj;
-        int it = 0;
+        int it = 0, next_check = ce > 0 ? ce : -1;  // iteration of the next stop-rule check
         bool stop = false;
         for (; it < a.iters; ++it) {
           float den = matvec_part(csh, c4);
           if (hf == 1 && j < K) psh[j] = den;
           __syncthreads();
           if (own) den += psh[j];
-          if (ce > 0 && it > 0 && it % ce == 0) {
+          if (it == next_check) {
+            next_check += ce;
             const float dj = own ? cj - cp : 0.f;
             if (hf == 0 && j < KP) dsh[j] = dj;
             __syncthreads();
