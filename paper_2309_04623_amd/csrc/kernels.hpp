@@ -232,9 +232,8 @@ size_t gram_lds_bytes(int K, int KP, int prec, int ahead);
 // form = true (required for KP <= 128, refused above): the launch only
 // forms G, b and the start of every frame (Gf, bf, cf; warm-start decision
 // included); launch_gram_iter then runs the iterations, one frame per
-// workgroup of ceil(K / 32) waves (two lanes per row of G).  form = false
-// (KP > 128): one
-// launch forms G and iterates each frame.
+// workgroup of ceil(K / 32) waves (two lanes per row of G).
+// form = false (KP > 128): one launch forms G and iterates each frame.
 hipError_t launch_gram(int kp, bool ragged, const GramArgs& a, int max_blocks, hipStream_t s,
                        int* grid_out, bool form = false);
 hipError_t launch_gram_iter(int kp, const GramArgs& a, hipStream_t s);
