@@ -350,7 +350,11 @@ def batched_leg(args, nmf, synth, lib, V, M, h, torch):
             "ms_per_batch": el * 1e3, "frames_per_s": F / el,
             "latency_us_p50": float(np.percentile(lat_us, 50)),
             "latency_us_p99": float(np.percentile(lat_us, 99)),
-            "algorithmic_tflops": flops / el / 1e12}
+            "algorithmic_tflops": flops / el / 1e12,
+            "mfma_roofline_frac": flops / el / 1e12 / (2500.0 / 3),
+            "roofline_note": "flops counted as the full Gram products 2 K^2 P_f (+ b and the "
+                             "iterations) against the bf16x3 peak (dense bf16 2500 TFLOP/s / 3); "
+                             "the kernel forms the 32-blocked upper triangle of G only"}
 
 
 def tolerance_leg(args, nmf, synth, h, torch):
